@@ -1,0 +1,247 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+brute force on tiny inputs, a library distance transform, lattice-point counts,
+closed forms of spheres, slabs and spheroids, and invariants stated in the paper.
+Each test is chosen so that a plausible slip in the oracle (a dropped term, a wrong
+sign or index, a transposed operand) fails it."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, ndimage, special
+
+from oracle import lt_oracle as O
+from paper_2504_05808_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- D, LT
+
+@pytest.mark.parametrize("shape", [(9, 11), (13, 6), (6, 7, 5), (7, 8, 9), (4, 12, 5)])
+def test_tier1_equals_literal_definition(shape):
+    """Early-exit distance search and unpruned ball scatter == exhaustive min / max."""
+    rng = synth.rng_for(hash(shape) % 1000)
+    for trial in range(4):
+        lab = synth.random_labels(rng, shape, n_labels=1 + trial, p_bg=0.1 * trial)
+        D = O.edt_sq(lab)
+        np.testing.assert_array_equal(D, O.edt_sq_brute(lab))
+        LT = O.local_thickness_sq(D)
+        np.testing.assert_array_equal(LT, O.local_thickness_sq_brute(lab, D))
+
+
+def test_tier1_full_and_touching_labels():
+    """No background at all: other labels and the image border are the only sites."""
+    lab = np.ones((6, 7, 8), dtype=np.int32)
+    lab[:, :, 4:] = 2
+    lab[2:4, 2:5, 1:3] = 3
+    D = O.edt_sq(lab)
+    np.testing.assert_array_equal(D, O.edt_sq_brute(lab))
+    np.testing.assert_array_equal(O.local_thickness_sq(D), O.local_thickness_sq_brute(lab, D))
+
+
+def _scipy_per_label(lab):
+    out = np.zeros(lab.shape, dtype=np.int64)
+    for l in np.unique(lab):
+        if l == 0:
+            continue
+        m = np.pad(lab == l, 1)                     # frame = outside = background
+        e = ndimage.distance_transform_edt(m)[tuple(slice(1, -1) for _ in lab.shape)]
+        out[lab == l] = np.rint(e[lab == l] ** 2).astype(np.int64)
+    return out
+
+
+def test_edt_matches_scipy_2d():
+    lab, _ = synth.cfg1()
+    np.testing.assert_array_equal(O.edt_sq(lab), _scipy_per_label(lab))
+
+
+def test_edt_matches_scipy_3d_touching():
+    rng = synth.rng_for(7)
+    lab = synth.random_labels(rng, (20, 17, 23), n_labels=5, blob=4)
+    np.testing.assert_array_equal(O.edt_sq(lab), _scipy_per_label(lab))
+
+
+def test_per_object_crops_equal_whole_image():
+    lab, _ = synth.cfg2()
+    d0, lt0, w0 = O.fields(lab, per_object=False)
+    d1, lt1, w1 = O.fields(lab, per_object=True)
+    np.testing.assert_array_equal(d0, d1)
+    np.testing.assert_array_equal(lt0, lt1)
+    assert w0 == w1
+
+
+def _golden_counts():
+    rows = []
+    with open(os.path.join(GOLDEN, "lattice_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(tuple(int(v) for v in line.split()))
+    return rows
+
+
+@pytest.mark.parametrize("ndim,r,count", _golden_counts())
+def test_digital_disc_ball(ndim, r, count):
+    """Digital disc/ball {|p - c|^2 <= r^2}: V is the lattice count, LT == r^2 + 1
+    everywhere, roundness is exactly 1 and sphericity is close to 1."""
+    m, _ = (synth.disc_mask if ndim == 2 else synth.ball_mask)(r)
+    lab = np.pad(m.astype(np.int32), 2)
+    res = O.measure(lab, per_object=False)
+    assert res["volume"][1] == count
+    assert np.all(res["lt_sq"][lab == 1] == r * r + 1)
+    assert res["max_lt_sq"][1] == r * r + 1
+    assert abs(res["roundness"][1] - 1.0) < 1e-12
+    if r >= 5:
+        assert abs(res["sphericity"][1] - 1.0) < 2e-3
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 4, 5, 8, 9])
+def test_slab(w):
+    """A slab of width w: centre D = ceil(w/2)^2 and, away from its ends, LT equals
+    ceil(w/2)^2 on every voxel across the width."""
+    h = 6 * w + 8
+    lab = np.zeros((h, w + 4), dtype=np.int32)
+    lab[:, 2:2 + w] = 1
+    D = O.edt_sq(lab)
+    LT = O.local_thickness_sq(D)
+    half = (w + 1) // 2
+    mid = slice(3 * w, 3 * w + 3)
+    assert D[mid, 2 + (w - 1) // 2].max() == half * half
+    assert np.all(LT[mid, 2:2 + w] == half * half)
+    assert np.all(LT[lab == 0] == 0)
+
+
+def test_invariants_random_shapes():
+    """LT >= D; max LT == max D per object; every LT value is a D value of the
+    same object; 0 < roundness <= 1 (Method, Roundness: the curvature estimate
+    cannot exceed the maximal inscribed radius; Results: it never reaches 0)."""
+    lab, _ = synth.cfg2()
+    res = O.measure(lab)
+    D, LT = res["dist_sq"], res["lt_sq"]
+    obj = lab != 0
+    assert np.all(LT[obj] >= D[obj])
+    assert np.all(LT[~obj] == 0)
+    for l in range(1, int(lab.max()) + 1):
+        sel = lab == l
+        assert LT[sel].max() == D[sel].max()
+        assert set(np.unique(LT[sel])) <= set(np.unique(D[sel]))
+    r = res["roundness"][1:]
+    assert np.all((r > 0) & (r <= 1 + 1e-12))
+
+
+# --------------------------------------------------------------------------- shell
+
+def test_shell_thin_and_cube():
+    lab = np.zeros((5, 9, 9), dtype=np.int32)
+    lab[2, 1:8, 1:8] = 1                       # one voxel thick: all shell
+    assert O.shell_mask(lab)[lab == 1].all()
+    cube = np.zeros((7, 7, 7), dtype=np.int32)
+    cube[2:5, 2:5, 2:5] = 4
+    sh = O.shell_mask(cube)
+    assert sh.sum() == 26 and not sh[3, 3, 3]
+
+
+def test_shell_face_neighbours_only_and_border():
+    sq = np.ones((5, 5), dtype=np.int32)
+    sq[0, 0] = 0                             # (1,1) has a background diagonal only
+    sh = O.shell_mask(sq)
+    assert not sh[1, 1]
+    assert sh[0, 1] and sh[4, 4]             # image border counts as outside
+    assert sh.sum() == 5 * 5 - 1 - 9
+    two = np.ones((4, 6), dtype=np.int32)
+    two[:, 3:] = 2                           # another label is a boundary too
+    assert O.shell_mask(two)[1:3, 2:4].all()
+
+
+# --------------------------------------------------------------------------- closed forms
+
+def _spheroid_quadrature(a, c):
+    """Surface of revolution of (a sin t, c cos t), t in [0, pi]."""
+    f = lambda t: 2 * math.pi * a * math.sin(t) * math.sqrt((a * math.cos(t)) ** 2 + (c * math.sin(t)) ** 2)
+    return integrate.quad(f, 0, math.pi, epsabs=1e-13, epsrel=1e-13)[0]
+
+
+@pytest.mark.parametrize("a,c", [(2, 1), (1, 2), (5, 0.3), (0.3, 5), (3, 3.0001), (3, 2.9999), (7, 7)])
+def test_spheroid_surface_quadrature(a, c):
+    assert O.spheroid_surface(a, c) == pytest.approx(_spheroid_quadrature(a, c), rel=1e-9)
+
+
+def test_spheroid_reading_of_eccentricity():
+    """The printed eccentricity (no square root) would give 39.397 for a=2, c=1;
+    the spheroid's surface is 34.6875."""
+    assert O.spheroid_surface(2.0, 1.0) == pytest.approx(34.6875, abs=5e-4)
+
+
+def test_ramanujan_perimeter():
+    assert O.ramanujan_perimeter(3.0, 3.0) == pytest.approx(2 * math.pi * 3.0, rel=1e-15)
+    for a, b, tol in [(2.0, 1.0, 1e-5), (1.0, 3.0, 1e-4), (6.0, 1.0, 1e-3)]:
+        exact = 4 * max(a, b) * special.ellipe(1 - (min(a, b) / max(a, b)) ** 2)
+        assert O.ramanujan_perimeter(a, b) == pytest.approx(exact, rel=tol)
+        assert abs(O.ramanujan_perimeter(a, b) / exact - 1) > 1e-8 or a == b
+
+
+def test_sphericity_of_sphere_and_circle_is_one():
+    for a in (0.7, 3.0, 40.0):
+        assert O.sphericity_3d(4.0 / 3.0 * math.pi * a ** 3, a) == pytest.approx(1.0, rel=1e-13)
+        assert O.sphericity_2d(math.pi * a * a, a) == pytest.approx(1.0, rel=1e-13)
+
+
+def test_sphericity_below_one_and_monotone():
+    """Wadell's sphericity is at most 1 (the sphere minimises surface at fixed
+    volume), and falls as the spheroid flattens or stretches away from a sphere."""
+    V = 1000.0
+    r0 = (3 * V / (4 * math.pi)) ** (1 / 3)
+    prev = 1.0
+    for k in [0.95, 0.8, 0.6, 0.4, 0.2]:
+        s = O.sphericity_3d(V, r0 * k)        # thinner a -> prolate
+        assert s < prev
+        prev = s
+    prev = 1.0
+    for k in [1.05, 1.3, 1.8, 2.5]:
+        s = O.sphericity_3d(V, r0 * k)        # wider a -> oblate
+        assert s < prev
+        prev = s
+    A = 500.0
+    rc = math.sqrt(A / math.pi)
+    for k in [0.9, 0.5, 1.2, 2.0]:
+        assert O.sphericity_2d(A, rc * k) < 1.0
+
+
+def test_sphericity_matches_wadell_on_spheroid_values():
+    """With the exact semi-axes of a spheroid, S_LT is Wadell's sphericity of that
+    spheroid: pi^(1/3) (6V)^(2/3) / S computed from its quadrature surface."""
+    for a, c in [(4.0, 1.5), (2.0, 6.0)]:
+        V = 4 / 3 * math.pi * a * a * c
+        ref = math.pi ** (1 / 3) * (6 * V) ** (2 / 3) / _spheroid_quadrature(a, c)
+        assert O.sphericity_3d(V, a) == pytest.approx(ref, rel=1e-9)
+
+
+def test_ellipse_sphericity_matches_perimeter_ratio():
+    for a, b in [(5.0, 2.0), (2.0, 9.0)]:
+        A = math.pi * a * b
+        exact_po = 4 * max(a, b) * special.ellipe(1 - (min(a, b) / max(a, b)) ** 2)
+        assert O.sphericity_2d(A, a) == pytest.approx(2 * math.sqrt(math.pi * A) / exact_po, rel=1e-3)
+
+
+def test_closed_forms_nan_for_absent_labels():
+    lab = np.zeros((8, 8, 8), dtype=np.int32)
+    lab[2:5, 2:5, 2:5] = 3
+    res = O.measure(lab, max_label=5)
+    assert len(res["sphericity"]) == 6
+    for l in (0, 1, 2, 4, 5):
+        assert math.isnan(res["sphericity"][l]) and res["volume"][l] == 0
+    assert res["volume"][3] == 27
+
+
+def test_measure_values_on_mixed_labels_are_per_object():
+    """Measures of an object do not depend on other objects touching it."""
+    m, _ = synth.ball_mask(6)
+    lab = np.pad(m.astype(np.int32), 3)
+    alone = O.measure(lab)
+    crowd = lab.copy()
+    crowd[(crowd == 0) & (np.indices(crowd.shape)[0] < 9)] = 2
+    both = O.measure(crowd)
+    for k in ("volume", "max_lt_sq", "shell_count"):
+        assert both[k][1] == alone[k][1]
+    for k in ("sum_lt", "shell_sum_lt", "sphericity", "roundness"):
+        assert both[k][1] == pytest.approx(alone[k][1], rel=1e-12)
