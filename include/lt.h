@@ -1,0 +1,162 @@
+/*
+ * liblt -- local-thickness sphericity and roundness on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Pieta, Rasmussen, Dahl, Christensen, "Fast Sphericity and Roundness
+ * approximation in 2D and 3D using Local Thickness" (arXiv 2504.05808).
+ *
+ * Pipeline over a labelled 2D image or 3D volume, all objects at once:
+ *   lt_edt              per-label squared Euclidean distance transform D
+ *   lt_thickness        squared local thickness LT_sq (largest inscribed ball
+ *                       containing each voxel; Method section)
+ *   lt_object_measures  per-object volume, mean / max / shell-mean local
+ *                       thickness, sphericity and roundness (Method: Sphericity
+ *                       and Roundness subsections)
+ *
+ * Conventions (shared by every call):
+ *   - ndim = 2 with shape = {ny, nx}, or ndim = 3 with shape = {nz, ny, nx};
+ *     C order, x contiguous, unit isotropic spacing; each extent <= 1024 in 3D
+ *     and <= 2048 in 2D.
+ *   - labels: LT_U16, LT_I32 or LT_U32; 0 is background; a label may hold several
+ *     connected components (it is still one object).  Every position outside the
+ *     image, and every voxel of another label, is background for an object.
+ *   - distances are squared, between voxel centres, in int32: a voxel next to
+ *     background has D = 1.  Balls are open and centred on lattice points.
+ *   - every pointer argument except `ctx` and `shape` is a DEVICE pointer; the
+ *     caller allocates and owns all inputs and outputs; the library never frees
+ *     caller memory.  `shape` is a host array.
+ *   - every call is stream-ordered on `stream` (a hipStream_t; NULL = the null
+ *     stream) and returns without synchronising.  Argument errors are reported
+ *     synchronously before anything is launched; errors found on the device
+ *     (label above max_label, negative int32 label) set a device error word that
+ *     lt_sync_status reads.
+ *   - no call aborts or throws across this interface.  A zero-size image is a
+ *     no-op returning LT_OK.
+ *   - calls on one context must not overlap in time (they share its scratch
+ *     memory); use one context per concurrent stream.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LT_OK = 0,
+    LT_E_ARG = 1,          /* null pointer or invalid argument */
+    LT_E_DTYPE = 2,        /* unknown label dtype */
+    LT_E_SHAPE = 3,        /* ndim not 2/3, negative or too large extent */
+    LT_E_ALLOC = 4,        /* device allocation failed */
+    LT_E_HIP = 5,          /* a HIP runtime call failed (see lt_last_error) */
+    LT_E_LABEL_RANGE = 6,  /* device: a label exceeded max_label or was negative */
+    LT_E_OVERFLOW = 7,     /* device: an intermediate exceeded its range */
+    LT_E_WORKSPACE = 8,    /* a caller-provided buffer is too small */
+    LT_E_NOT_READY = 9     /* object not initialised (e.g. model not trained) */
+} lt_status;
+
+typedef enum { LT_U16 = 1, LT_I32 = 2, LT_U32 = 3 } lt_dtype;
+
+typedef struct lt_ctx lt_ctx;
+
+/* Create a context bound to HIP device `device` (the device is made current for
+ * the calls on it).  Owns scratch memory, lookup tables and a device error word. */
+lt_status lt_ctx_create(lt_ctx** out, int device);
+/* Free the context's device memory (synchronises the device first). */
+lt_status lt_ctx_destroy(lt_ctx* ctx);
+
+/* Per-label squared Euclidean distance transform (the distance map underlying the
+ * local-thickness definition; Introduction and Method, first paragraph):
+ *   dist_sq[p] = 0 where labels[p] == 0, otherwise
+ *   dist_sq[p] = min |p - q|^2 over lattice points q outside the image or with
+ *                labels[q] != labels[p].
+ * labels: [N] of `dtype`; dist_sq: [N] int32 output (N = product of shape). */
+lt_status lt_edt(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                 const int64_t* shape, int32_t* dist_sq, void* stream);
+
+/* Squared local thickness (Method, first paragraph: the radius of the largest
+ * inscribed circle/sphere containing the point):
+ *   lt_sq[p] = max{ dist_sq[x] : |p - x|^2 < dist_sq[x] } for object voxels,
+ *   lt_sq[p] = 0 on background.
+ * The reported radius is sqrt(lt_sq).  dist_sq must be lt_edt's output for the
+ * same labels.  max_label bounds the label values (work is organised per object);
+ * a larger label sets LT_E_LABEL_RANGE on the device.  lt_sq: [N] int32 output. */
+lt_status lt_thickness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                       const int64_t* shape, const int32_t* dist_sq, uint32_t max_label,
+                       int32_t* lt_sq, void* stream);
+
+/* Per-object outputs, each an array of max_label + 1 entries indexed by label value.
+ * Entry 0 (background) and absent labels have volume 0 and NaN measures. */
+typedef struct {
+    uint64_t* volume;         /* V (3D) or area A (2D): voxel count */
+    uint64_t* shell_count;    /* voxels with a face neighbour (4 in 2D, 6 in 3D)
+                                 outside the image or of another label */
+    int32_t* max_lt_sq;       /* max LT_sq over the object: squared radius R^2 of the
+                                 maximal inscribed ball (Method, Roundness) */
+    float* mean_lt;           /* mean of sqrt(LT_sq) over the object */
+    float* shell_mean_lt;     /* mean of sqrt(LT_sq) over the shell */
+    float* sphericity;        /* 3D: pi^(1/3) (6V)^(2/3) / S, S the surface of the
+                                 spheroid with equal semi-axes a = mean_lt and third
+                                 semi-axis c = 3V / (4 pi a^2) (Background Eq. 1;
+                                 Method, Sphericity).  2D: P_c / P_o with P_c =
+                                 2 sqrt(pi A) and P_o Ramanujan's first
+                                 approximation for semi-axes a = mean_lt and
+                                 b = A / (pi a) */
+    float* roundness;         /* shell_mean_lt / sqrt(max_lt_sq) (Method, Roundness) */
+    float* hist32;            /* optional, may be NULL: [(max_label + 1) * 32]
+                                 fraction of the object's voxels in bin k = 1..32
+                                 (stored at k - 1), bin(p) = the smallest k with
+                                 1024 * LT_sq(p) <= k^2 * max_lt_sq */
+} lt_measures;
+
+/* Shell extraction, per-object reductions and closed forms.  lt_sq must be
+ * lt_thickness's output for the same labels.  Output arrays are device arrays
+ * of max_label + 1 entries; they are fully written. */
+lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                             const int64_t* shape, const int32_t* lt_sq, uint32_t max_label,
+                             const lt_measures* out, void* stream);
+
+/* Closed forms alone, from per-object sums held on the device (the last step of
+ * lt_object_measures; exposed for callers that accumulate their own sums):
+ *   mean_lt = sum_lt_q23 / 2^23 / volume, shell_mean_lt = shell_sum_q23 / 2^23 /
+ *   shell_count, roundness = shell_mean_lt / sqrt(max_lt_sq), sphericity from the
+ *   spheroid (ndim 3) or ellipse (ndim 2) model as in lt_measures.
+ * The radius sums are Q.23 fixed point (round(sqrt(LT_sq) * 2^23) summed).  All
+ * arrays have n entries; entries with volume 0 get NaN. */
+lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
+                          const int32_t* max_lt_sq, const uint64_t* shell_count,
+                          const uint64_t* shell_sum_q23, uint32_t n, int ndim, float* mean_lt,
+                          float* shell_mean_lt, float* sphericity, float* roundness,
+                          void* stream);
+
+/* Synchronise `stream`, read and clear the context's device error word.
+ * Returns LT_OK, LT_E_LABEL_RANGE, LT_E_OVERFLOW or LT_E_HIP. */
+lt_status lt_sync_status(lt_ctx* ctx, void* stream);
+
+/* Kernel timing (tracing).  When enabled, every kernel the library launches is
+ * bracketed by two HIP events recorded on the launch stream; lt_profile_read waits
+ * for the pending events and returns per-kernel totals accumulated since the last
+ * lt_profile_reset: up to `cap` entries are written to `out` (host array) and the
+ * number of distinct kernels to *n_out.  Disabled by default. */
+typedef struct {
+    char name[40];
+    double total_ms;
+    uint64_t launches;
+} lt_kernel_time;
+lt_status lt_profile_enable(lt_ctx* ctx, int on);
+lt_status lt_profile_read(lt_ctx* ctx, lt_kernel_time* out, int cap, int* n_out);
+lt_status lt_profile_reset(lt_ctx* ctx);
+
+/* Static text for a status code. */
+const char* lt_status_str(lt_status s);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* lt_last_error(void);
+/* Library version string. */
+const char* lt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LT_H */

@@ -241,6 +241,29 @@ def closed_forms(sums: dict, ndim: int) -> dict:
                 roundness=rnd)
 
 
+def lt_histogram(labels: np.ndarray, lt_sq: np.ndarray, max_lt_sq: np.ndarray) -> np.ndarray:
+    """Normalised 32-bin histogram of sqrt(LT_sq) / R per label (R^2 = the object's
+    largest LT_sq): bin(p) is the smallest k in 1..32 with 1024 LT_sq(p) <= k^2 R^2,
+    decided in integers.  Row l holds the fractions of label l's voxels in bins
+    1..32; rows of absent labels are NaN.  (Feature of the learned correction, not
+    a quantity of the paper.)"""
+    lab = np.asarray(labels).astype(np.int64).ravel()
+    lt = np.asarray(lt_sq, dtype=np.int64).ravel()
+    n = len(max_lt_sq)
+    obj = lab != 0
+    l, v = lab[obj], lt[obj]
+    r2 = np.asarray(max_lt_sq, dtype=np.int64)[l]
+    k = np.arange(1, 33, dtype=np.int64)
+    ok = 1024 * v[:, None] <= (k[None, :] ** 2) * r2[:, None]
+    bins = np.argmax(ok, axis=1)                    # first k satisfying the test
+    counts = np.zeros((n, 32), dtype=np.int64)
+    np.add.at(counts, (l, bins), 1)
+    V = counts.sum(axis=1)
+    out = np.full((n, 32), np.nan)
+    out[V > 0] = counts[V > 0] / V[V > 0, None]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # whole pipeline
 # ---------------------------------------------------------------------------

@@ -1,0 +1,305 @@
+// C-ABI entry points of liblt: context, argument checks, dispatch, error text.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "lt_internal.h"
+
+namespace lt {
+
+static thread_local char g_err[512] = "";
+
+lt_status set_error(lt_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+lt_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LT_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return set_error(LT_E_ALLOC, "%s: %s", what, hipGetErrorString(e));
+    return set_error(LT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+lt_status ensure_scratch(lt_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->scratch.bytes) return LT_OK;
+    if (ctx->scratch.ptr) {
+        lt_status st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (st) return st;
+        (void)hipFree(ctx->scratch.ptr);
+        ctx->scratch.ptr = nullptr;
+        ctx->scratch.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8 + (1u << 20);
+    void* p = nullptr;
+    lt_status st = hip_check(hipMalloc(&p, want), "hipMalloc(scratch)");
+    if (st) return st;
+    ctx->scratch.ptr = p;
+    ctx->scratch.bytes = want;
+    return LT_OK;
+}
+
+lt_status geom_from(int ndim, const int64_t* shape, Geom* g) {
+    if (!shape) return set_error(LT_E_ARG, "shape is NULL");
+    if (ndim != 2 && ndim != 3) return set_error(LT_E_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
+    const int64_t lim = ndim == 3 ? 1024 : 2048;
+    for (int i = 0; i < ndim; ++i) {
+        if (shape[i] < 0) return set_error(LT_E_SHAPE, "negative extent %lld", (long long)shape[i]);
+        if (shape[i] > lim)
+            return set_error(LT_E_SHAPE, "extent %lld exceeds %lld", (long long)shape[i], (long long)lim);
+    }
+    g->ndim = ndim;
+    g->nz = ndim == 3 ? (int)shape[0] : 1;
+    g->ny = (int)shape[ndim - 2];
+    g->nx = (int)shape[ndim - 1];
+    g->n = (size_t)g->nz * g->ny * g->nx;
+    return LT_OK;
+}
+
+// Containment tables for the exact centre prune: for a neighbour offset o and
+// squared radius d, T[d] = max{ |q - o|^2 : q in Z^n, |q|^2 < d }.  A ball of
+// squared radius d centred at x lies inside the open ball of x + o iff
+// D(x + o) > T[d].  By lattice symmetry T depends only on |o|^2.
+static void build_prune_tables(int n, std::vector<int32_t>& out) {
+    const int dcap = PRUNE_DCAP;
+    const int r = 129;                          // r*r > dcap
+    const int nk = n;                           // |o|^2 = 1 .. n
+    std::vector<int32_t> best((size_t)nk * (dcap + 1), -1);
+    const int rz = n == 3 ? r : 0;
+    for (int qz = -rz; qz <= rz; ++qz)
+        for (int qy = -r; qy <= r; ++qy)
+            for (int qx = -r; qx <= r; ++qx) {
+                int m = qz * qz + qy * qy + qx * qx;
+                if (m > dcap) continue;
+                for (int k = 1; k <= nk; ++k) {
+                    // o_k = (1, 0, 0), (1, 1, 0), (1, 1, 1) in (x, y, z) order
+                    int ox = 1, oy = k >= 2 ? 1 : 0, oz = k >= 3 ? 1 : 0;
+                    int dx = qx - ox, dy = qy - oy, dz = qz - oz;
+                    int v = dx * dx + dy * dy + dz * dz;
+                    int32_t& b = best[(size_t)(k - 1) * (dcap + 1) + m];
+                    if (v > b) b = v;
+                }
+            }
+    out.assign((size_t)nk * (dcap + 1), -1);
+    for (int k = 0; k < nk; ++k) {
+        int32_t run = -1;                        // max over |q|^2 < d
+        for (int d = 0; d <= dcap; ++d) {
+            out[(size_t)k * (dcap + 1) + d] = run;
+            int32_t b = best[(size_t)k * (dcap + 1) + d];
+            if (b > run) run = b;
+        }
+    }
+}
+
+static std::once_flag g_tab_once;
+static std::vector<int32_t> g_tab3, g_tab2;
+
+}  // namespace lt
+
+using namespace lt;
+
+extern "C" {
+
+const char* lt_version(void) { return "liblt 0.1 (gfx950)"; }
+
+const char* lt_last_error(void) { return g_err; }
+
+const char* lt_status_str(lt_status s) {
+    switch (s) {
+        case LT_OK: return "ok";
+        case LT_E_ARG: return "invalid argument";
+        case LT_E_DTYPE: return "invalid label dtype";
+        case LT_E_SHAPE: return "invalid shape";
+        case LT_E_ALLOC: return "device allocation failed";
+        case LT_E_HIP: return "HIP runtime error";
+        case LT_E_LABEL_RANGE: return "label out of range";
+        case LT_E_OVERFLOW: return "range overflow";
+        case LT_E_WORKSPACE: return "workspace too small";
+        case LT_E_NOT_READY: return "not ready";
+    }
+    return "unknown status";
+}
+
+lt_status lt_ctx_create(lt_ctx** out, int device) {
+    if (!out) return set_error(LT_E_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    lt_status st = hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
+    if (st) return st;
+    if (device < 0 || device >= count)
+        return set_error(LT_E_ARG, "device %d not present (%d devices)", device, count);
+    st = hip_check(hipSetDevice(device), "hipSetDevice");
+    if (st) return st;
+    lt_ctx* c = new (std::nothrow) lt_ctx();
+    if (!c) return set_error(LT_E_ALLOC, "host allocation failed");
+    c->device = device;
+    hipDeviceProp_t prop;
+    if ((st = hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties"))) {
+        delete c;
+        return st;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    std::call_once(g_tab_once, [] {
+        build_prune_tables(3, g_tab3);
+        build_prune_tables(2, g_tab2);
+    });
+    size_t b3 = g_tab3.size() * sizeof(int32_t), b2 = g_tab2.size() * sizeof(int32_t);
+    if ((st = hip_check(hipMalloc((void**)&c->d_err, sizeof(uint32_t)), "hipMalloc(err)")) ||
+        (st = hip_check(hipMalloc((void**)&c->d_prune3, b3), "hipMalloc(tab3)")) ||
+        (st = hip_check(hipMalloc((void**)&c->d_prune2, b2), "hipMalloc(tab2)")) ||
+        (st = hip_check(hipMemcpy(c->d_prune3, g_tab3.data(), b3, hipMemcpyHostToDevice), "copy tab3")) ||
+        (st = hip_check(hipMemcpy(c->d_prune2, g_tab2.data(), b2, hipMemcpyHostToDevice), "copy tab2")) ||
+        (st = hip_check(hipMemset(c->d_err, 0, sizeof(uint32_t)), "clear err"))) {
+        lt_ctx_destroy(c);
+        return st;
+    }
+    *out = c;
+    return LT_OK;
+}
+
+lt_status lt_ctx_destroy(lt_ctx* ctx) {
+    if (!ctx) return LT_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch.ptr) (void)hipFree(ctx->scratch.ptr);
+    if (ctx->d_err) (void)hipFree(ctx->d_err);
+    if (ctx->d_prune3) (void)hipFree(ctx->d_prune3);
+    if (ctx->d_prune2) (void)hipFree(ctx->d_prune2);
+    delete ctx;
+    return LT_OK;
+}
+
+static lt_status common_checks(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                               const int64_t* shape, Geom* g) {
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    if (dtype != LT_U16 && dtype != LT_I32 && dtype != LT_U32)
+        return set_error(LT_E_DTYPE, "unknown label dtype %d", (int)dtype);
+    lt_status st = geom_from(ndim, shape, g);
+    if (st) return st;
+    if (g->n > 0 && !labels) return set_error(LT_E_ARG, "labels is NULL");
+    return hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+}
+
+lt_status lt_edt(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                 int32_t* dist_sq, void* stream) {
+    Geom g;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st) return st;
+    if (g.n == 0) return LT_OK;
+    if (!dist_sq) return set_error(LT_E_ARG, "dist_sq is NULL");
+    return launch_edt(ctx, labels, dtype, g, dist_sq, (hipStream_t)stream);
+}
+
+lt_status lt_thickness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                       const int64_t* shape, const int32_t* dist_sq, uint32_t max_label,
+                       int32_t* lt_sq, void* stream) {
+    Geom g;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st) return st;
+    if (g.n == 0) return LT_OK;
+    if (!dist_sq || !lt_sq) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    return launch_thickness(ctx, labels, dtype, g, dist_sq, max_label, lt_sq, (hipStream_t)stream);
+}
+
+lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                             const int64_t* shape, const int32_t* lt_sq, uint32_t max_label,
+                             const lt_measures* out, void* stream) {
+    Geom g;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st) return st;
+    if (!out || !out->volume || !out->shell_count || !out->max_lt_sq || !out->mean_lt ||
+        !out->shell_mean_lt || !out->sphericity || !out->roundness)
+        return set_error(LT_E_ARG, "an output array of lt_measures is NULL");
+    if (g.n > 0 && !lt_sq) return set_error(LT_E_ARG, "lt_sq is NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    return launch_measures(ctx, labels, dtype, g, lt_sq, max_label, out, (hipStream_t)stream);
+}
+
+lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
+                          const int32_t* max_lt_sq, const uint64_t* shell_count,
+                          const uint64_t* shell_sum_q23, uint32_t n, int ndim, float* mean_lt,
+                          float* shell_mean_lt, float* sphericity, float* roundness,
+                          void* stream) {
+    if (ndim != 2 && ndim != 3) return set_error(LT_E_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
+    if (n == 0) return LT_OK;
+    if (!volume || !sum_lt_q23 || !max_lt_sq || !shell_count || !shell_sum_q23 || !mean_lt ||
+        !shell_mean_lt || !sphericity || !roundness)
+        return set_error(LT_E_ARG, "an array is NULL");
+    return launch_closed_forms(volume, sum_lt_q23, max_lt_sq, shell_count, shell_sum_q23, n, ndim,
+                               mean_lt, shell_mean_lt, sphericity, roundness, (hipStream_t)stream);
+}
+
+lt_status lt_profile_enable(lt_ctx* ctx, int on) {
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    ctx->profile = on != 0;
+    return LT_OK;
+}
+
+lt_status lt_profile_read(lt_ctx* ctx, lt_kernel_time* out, int cap, int* n_out) {
+    if (!ctx || (cap > 0 && !out)) return set_error(LT_E_ARG, "ctx or out is NULL");
+    lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    if (st) return st;
+    for (const PendingTiming& p : ctx->pending) {
+        float ms = 0.f;
+        if (!st) st = hip_check(hipEventSynchronize(p.stop), "hipEventSynchronize");
+        if (!st) st = hip_check(hipEventElapsedTime(&ms, p.start, p.stop), "hipEventElapsedTime");
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+        if (st) continue;
+        KernelTotal* t = nullptr;
+        for (KernelTotal& k : ctx->totals)
+            if (strcmp(k.name, p.name) == 0) t = &k;
+        if (!t) {
+            ctx->totals.push_back(KernelTotal{p.name, 0.0, 0});
+            t = &ctx->totals.back();
+        }
+        t->ms += ms;
+        t->launches += 1;
+    }
+    ctx->pending.clear();
+    if (st) return st;
+    int n = 0;
+    for (const KernelTotal& k : ctx->totals) {
+        if (n < cap) {
+            snprintf(out[n].name, sizeof(out[n].name), "%s", k.name);
+            out[n].total_ms = k.ms;
+            out[n].launches = k.launches;
+        }
+        ++n;
+    }
+    if (n_out) *n_out = n;
+    return LT_OK;
+}
+
+lt_status lt_profile_reset(lt_ctx* ctx) {
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    int n = 0;
+    lt_status st = lt_profile_read(ctx, nullptr, 0, &n);
+    ctx->totals.clear();
+    return st;
+}
+
+lt_status lt_sync_status(lt_ctx* ctx, void* stream) {
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t err = 0;
+    if ((st = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return st;
+    if ((st = hip_check(hipMemcpy(&err, ctx->d_err, sizeof(err), hipMemcpyDeviceToHost), "read err")))
+        return st;
+    if ((st = hip_check(hipMemset(ctx->d_err, 0, sizeof(uint32_t)), "clear err"))) return st;
+    if (err & ERR_LABEL) return set_error(LT_E_LABEL_RANGE, "a label exceeded max_label or was negative");
+    if (err & ERR_OVERFLOW) return set_error(LT_E_OVERFLOW, "an intermediate exceeded its range");
+    return LT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal declarations shared by the liblt translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <vector>
+
+#include "../../include/lt.h"
+
+namespace lt {
+
+// Device error word bits.
+enum : uint32_t { ERR_LABEL = 1u, ERR_OVERFLOW = 2u };
+
+// Largest squared radius covered by the exact containment-prune tables.  Centres
+// with a larger D are kept without testing (always exact, only less pruning).
+constexpr int PRUNE_DCAP = 16384;
+
+// Paint tile: target rows x columns of one work item (columns along x).
+constexpr int TILE_Y = 32;
+constexpr int TILE_X = 64;
+constexpr int TILE_LEVELS = 7;                 // interval lengths 1..64 -> levels 0..6
+
+// Packed z-front entry (3D): bits 0..18 D of the centre, 19..28 dz + 512 (dz is
+// the slice minus the centre's z), 29..31 (plane 0 only) number of entries.
+constexpr uint32_t ZF_D_BITS = 19;
+constexpr uint32_t ZF_D_MASK = (1u << ZF_D_BITS) - 1u;
+constexpr uint32_t ZF_DZ_SHIFT = 19;
+constexpr uint32_t ZF_DZ_MASK = 1023u;
+constexpr uint32_t ZF_N_SHIFT = 29;
+constexpr int ZF_PLANES = 3;
+
+// Column-list entry (3D): (D << 11) | z.
+constexpr uint32_t CL_Z_BITS = 11;
+constexpr uint32_t CL_Z_MASK = (1u << CL_Z_BITS) - 1u;
+
+struct Geom {
+    int ndim;
+    int nz, ny, nx;     // ndim == 2: nz == 1
+    size_t n;           // voxel count
+};
+
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// One timed launch: events recorded on the launch stream around the kernel.
+struct PendingTiming {
+    const char* name;
+    hipEvent_t start, stop;
+};
+
+struct KernelTotal {
+    const char* name;
+    double ms;
+    uint64_t launches;
+};
+
+}  // namespace lt
+
+struct lt_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t lds_per_block = 0;
+    uint32_t* d_err = nullptr;          // device error word
+    int32_t* d_prune3 = nullptr;        // [3][PRUNE_DCAP + 1] (|o|^2 = 1, 2, 3)
+    int32_t* d_prune2 = nullptr;        // [2][PRUNE_DCAP + 1] (|o|^2 = 1, 2)
+    lt::Scratch scratch;                // grows on demand, freed by lt_ctx_destroy
+    bool profile = false;               // time every launch with HIP events
+    std::vector<lt::PendingTiming> pending;
+    std::vector<lt::KernelTotal> totals;
+};
+
+namespace lt {
+
+// Host helpers (api.hip).
+lt_status set_error(lt_status s, const char* fmt, ...);
+lt_status hip_check(hipError_t e, const char* what);
+lt_status ensure_scratch(lt_ctx* ctx, size_t bytes);
+lt_status geom_from(int ndim, const int64_t* shape, Geom* g);
+
+// Launchers (edt.hip, thickness.hip, measures.hip).  All are stream-ordered.
+lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                     int32_t* dist_sq, hipStream_t s);
+size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label);
+lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                           const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
+                           hipStream_t s);
+size_t measures_scratch_bytes(uint32_t max_label);
+lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                          const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
+                          hipStream_t s);
+lt_status launch_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q,
+                              const int32_t* max_lt_sq, const uint64_t* shell_count,
+                              const uint64_t* shell_sum_q, uint32_t n, int ndim,
+                              float* mean_lt, float* shell_mean_lt, float* sphericity,
+                              float* roundness, hipStream_t s);
+
+// Brackets one kernel launch with HIP events on its stream when the context's
+// profiler is on (lt_profile_enable); the elapsed times are collected by
+// lt_profile_read.
+struct ProfScope {
+    lt_ctx* ctx;
+    hipStream_t s;
+    const char* name;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(lt_ctx* c, hipStream_t st, const char* n) : ctx(c), s(st), name(n) {
+        if (ctx && ctx->profile && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+        else
+            a = b = nullptr;
+    }
+    ~ProfScope() {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            ctx->pending.push_back(PendingTiming{name, a, b});
+        }
+    }
+};
+
+// Fixed-point scale of the deterministic radius sums (Q.23 in uint64).
+constexpr double SUM_SCALE = 8388608.0;
+
+// ---------------------------------------------------------------- device helpers
+
+// floor(sqrt(n)) for 0 <= n < 2^30, exact: float estimate then one-step fix-ups.
+__device__ __forceinline__ int isqrt_floor(int n) {
+    int r = (int)__fsqrt_rn((float)n);
+    if (r * r > n) --r;
+    else if ((r + 1) * (r + 1) <= n) ++r;
+    return r;
+}
+
+// Largest h with h*h < b, for b >= 1 (the reach of an open ball of squared radius b).
+__device__ __forceinline__ int open_reach(int b) { return isqrt_floor(b - 1); }
+
+template <typename L>
+__device__ __forceinline__ bool label_negative(L v) {
+    if constexpr (sizeof(L) == 4 && L(-1) < L(0)) return v < 0;
+    else return false;
+}
+
+}  // namespace lt

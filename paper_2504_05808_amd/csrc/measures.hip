@@ -1,0 +1,263 @@
+// Shell extraction, per-object reductions and closed forms.
+//
+// Method, Roundness: contour / surface voxels are object voxels with a background
+// neighbour in the 4-neighbourhood (2D) or the corresponding 6 face neighbours
+// (3D); here outside the image and other labels count as background.  Roundness is
+// the mean local thickness over those voxels divided by the object's largest local
+// thickness, the radius of the maximal inscribed circle/sphere.
+// Method, Sphericity: a spheroid (3D) or ellipse (2D) with semi-axis a = mean local
+// thickness and the object's volume / area replaces the measured surface /
+// perimeter in Wadell's sphericity (Background, Eq. 1) or the perimeter
+// sphericity P_c / P_o.
+//
+// Sums of radii are accumulated in Q.23 fixed point in uint64, so results do not
+// depend on atomic order.  A wave reduces each run of equal labels among its 64
+// lanes (consecutive x) and issues one set of atomics per run.
+#include <math.h>
+
+#include "lt_internal.h"
+
+namespace lt {
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    unsigned long long w = (unsigned long long)v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) w += __shfl_xor(w, off, 64);
+    return (uint64_t)w;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void zero_measure_arrays(uint64_t* vol, uint64_t* shc, int32_t* mx, uint64_t* sq,
+                                    uint64_t* ssq, uint32_t nlab) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlab) return;
+    vol[l] = 0;
+    shc[l] = 0;
+    mx[l] = 0;
+    sq[l] = 0;
+    ssq[l] = 0;
+}
+
+template <int NDIM, typename L>
+__global__ void __launch_bounds__(256)
+object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, int ny, int nz,
+            uint32_t max_label, uint64_t* __restrict__ vol, uint64_t* __restrict__ shc,
+            int32_t* __restrict__ mx, uint64_t* __restrict__ sq, uint64_t* __restrict__ ssq,
+            uint32_t* err) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const size_t plane = (size_t)ny * nx;
+    const size_t i = (size_t)z * plane + (size_t)y * nx + x;
+    uint64_t l = 0;
+    int v = 0;
+    bool shell = false;
+    uint64_t q = 0;
+    if (x < nx) {
+        const L raw = lab[i];
+        if (raw != 0) {
+            if (label_negative(raw) || (uint64_t)raw > max_label) {
+                atomicOr(err, ERR_LABEL);
+            } else {
+                l = (uint64_t)raw;
+                v = lt[i];
+                q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
+                shell = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 ||
+                        lab[i - 1] != raw || lab[i + 1] != raw || lab[i - nx] != raw ||
+                        lab[i + nx] != raw;
+                if (NDIM == 3 && !shell)
+                    shell = z == 0 || z == nz - 1 || lab[i - plane] != raw || lab[i + plane] != raw;
+            }
+        }
+    }
+    uint64_t active = __ballot(l != 0);
+    while (active) {
+        const int lead = __ffsll((unsigned long long)active) - 1;
+        const uint64_t L0 = (uint64_t)__shfl((unsigned long long)l, lead, 64);
+        const bool in = (l == L0);
+        const uint64_t m = __ballot(in);
+        const uint64_t sm = __ballot(in && shell);
+        const uint64_t s1 = wave_sum_u64(in ? q : 0);
+        const uint64_t s2 = wave_sum_u64(in && shell ? q : 0);
+        const int m1 = wave_max_i32(in ? v : 0);
+        if ((int)(threadIdx.x & 63) == lead) {
+            atomicAdd((unsigned long long*)&vol[L0], (unsigned long long)__popcll(m));
+            atomicAdd((unsigned long long*)&sq[L0], (unsigned long long)s1);
+            atomicMax(&mx[L0], m1);
+            if (sm) {
+                atomicAdd((unsigned long long*)&shc[L0], (unsigned long long)__popcll(sm));
+                atomicAdd((unsigned long long*)&ssq[L0], (unsigned long long)s2);
+            }
+        }
+        active &= ~m;
+    }
+}
+
+// Local-thickness histogram (32 bins of sqrt(LT_sq) / R, R^2 = the object's max):
+// bin k (1..32) is the smallest k with 1024 * LT_sq <= k^2 * R^2, decided in integers.
+template <typename L>
+__global__ void __launch_bounds__(256)
+lt_histogram(const L* __restrict__ lab, const int32_t* __restrict__ lt, size_t n,
+             uint32_t max_label, const int32_t* __restrict__ mx, uint32_t* __restrict__ hist) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const L raw = lab[i];
+    if (raw == 0 || label_negative(raw) || (uint64_t)raw > max_label) return;
+    const uint32_t l = (uint32_t)raw;
+    const int64_t num = 1024 * (int64_t)lt[i];
+    const int64_t r2 = mx[l];
+    if (r2 <= 0) return;
+    int k = (int)ceil(32.0 * sqrt((double)lt[i] / (double)r2));
+    k = min(max(k, 1), 32);
+    while (k < 32 && (int64_t)k * k * r2 < num) ++k;
+    while (k > 1 && (int64_t)(k - 1) * (k - 1) * r2 >= num) --k;
+    atomicAdd(&hist[(size_t)l * 32 + (k - 1)], 1u);
+}
+
+// Surface of the spheroid with equal semi-axes a and third semi-axis c, in FP32
+// with forms that stay accurate near the sphere and for extreme elongation:
+// with q = min(a, c) / max(a, c), e^2 = (1 - q)(1 + q);
+//   oblate  (c < a): S = 2 pi a^2 (1 + q^2 artanh(e) / e),  artanh(e) = log((1 + e) / q);
+//   prolate (c > a): S = 2 pi a^2 (1 + asin(e) / (q e)),     asin(e)   = atan2(e, q);
+// and Taylor series of artanh(e)/e and asin(e)/e in e^2 when e^2 < 2^-7.
+__device__ float spheroid_surface_f32(float a, float c) {
+    const float two_pi_a2 = 6.2831853f * a * a;
+    if (c == a) return 2.0f * two_pi_a2;
+    const bool oblate = c < a;
+    const float q = oblate ? c / a : a / c;
+    const float e2 = (1.0f - q) * (1.0f + q);
+    float ratio;                                  // artanh(e)/e or asin(e)/e
+    if (e2 < 0.0078125f) {
+        if (oblate)
+            ratio = 1.0f + e2 * (1.0f / 3.0f + e2 * (1.0f / 5.0f + e2 * (1.0f / 7.0f + e2 * (1.0f / 9.0f))));
+        else
+            ratio = 1.0f + e2 * (1.0f / 6.0f + e2 * (3.0f / 40.0f + e2 * (5.0f / 112.0f + e2 * (35.0f / 1152.0f))));
+    } else {
+        const float e = sqrtf(e2);
+        ratio = oblate ? logf((1.0f + e) / q) / e : atan2f(e, q) / e;
+    }
+    return oblate ? two_pi_a2 * (1.0f + q * q * ratio) : two_pi_a2 * (1.0f + ratio / q);
+}
+
+__global__ void closed_forms_kernel(const uint64_t* __restrict__ vol, const uint64_t* __restrict__ sq,
+                                    const int32_t* __restrict__ mx, const uint64_t* __restrict__ shc,
+                                    const uint64_t* __restrict__ ssq, uint32_t nlab, int ndim,
+                                    float* __restrict__ mean_lt, float* __restrict__ shell_mean,
+                                    float* __restrict__ sph, float* __restrict__ rnd,
+                                    const uint32_t* __restrict__ hist, float* __restrict__ hist_out) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlab) return;
+    const float nan = __int_as_float(0x7fc00000);
+    const uint64_t V = vol[l];
+    if (V == 0) {
+        mean_lt[l] = shell_mean[l] = sph[l] = rnd[l] = nan;
+        if (hist_out)
+            for (int k = 0; k < 32; ++k) hist_out[(size_t)l * 32 + k] = nan;
+        return;
+    }
+    const float a = (float)((double)sq[l] / SUM_SCALE / (double)V);
+    const float Vf = (float)V;
+    const float R = sqrtf((float)mx[l]);
+    mean_lt[l] = a;
+    const uint64_t ns = shc[l];
+    if (ns) {
+        const float sm = (float)((double)ssq[l] / SUM_SCALE / (double)ns);
+        shell_mean[l] = sm;
+        rnd[l] = sm / R;
+    } else {
+        shell_mean[l] = rnd[l] = nan;
+    }
+    const float pi = 3.14159265f;
+    if (ndim == 3) {
+        const float c = 3.0f * Vf / (4.0f * pi * a * a);
+        const float S = spheroid_surface_f32(a, c);
+        const float k6 = cbrtf(6.0f * Vf);
+        sph[l] = 1.46459189f * k6 * k6 / S;      // pi^(1/3) (6V)^(2/3) / S
+    } else {
+        const float b = Vf / (pi * a);
+        const float po = pi * (3.0f * (a + b) - sqrtf((3.0f * a + b) * (a + 3.0f * b)));
+        sph[l] = 2.0f * sqrtf(pi * Vf) / po;
+    }
+    if (hist_out) {
+        const float inv = 1.0f / Vf;
+        for (int k = 0; k < 32; ++k) hist_out[(size_t)l * 32 + k] = (float)hist[(size_t)l * 32 + k] * inv;
+    }
+}
+
+static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t measures_scratch_bytes(uint32_t max_label) {
+    const size_t nlab = (size_t)max_label + 1;
+    return 2 * align256(nlab * sizeof(uint64_t)) + align256(nlab * 32 * sizeof(uint32_t));
+}
+
+template <typename L>
+static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
+                                uint32_t max_label, const lt_measures* out, hipStream_t s) {
+    const size_t nlab = (size_t)max_label + 1;
+    lt_status st = ensure_scratch(ctx, measures_scratch_bytes(max_label));
+    if (st) return st;
+    char* base = (char*)ctx->scratch.ptr;
+    uint64_t* sq = (uint64_t*)base;
+    uint64_t* ssq = (uint64_t*)(base + align256(nlab * sizeof(uint64_t)));
+    uint32_t* hist = (uint32_t*)(base + 2 * align256(nlab * sizeof(uint64_t)));
+    const unsigned lb = (unsigned)((nlab + 255) / 256);
+    {
+        ProfScope _p(ctx, s, "zero_measure_arrays");
+        zero_measure_arrays<<<lb, 256, 0, s>>>(out->volume, out->shell_count, out->max_lt_sq, sq, ssq,
+                                               (uint32_t)nlab);
+    }
+    if (g.n > 0) {
+        ProfScope _p(ctx, s, "object_sums");
+        const dim3 grid((g.nx + 255) / 256, g.ny, g.nz);
+        if (g.ndim == 3)
+            object_sums<3, L><<<grid, 256, 0, s>>>(lab, lt, g.nx, g.ny, g.nz, max_label, out->volume,
+                                                   out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
+        else
+            object_sums<2, L><<<grid, 256, 0, s>>>(lab, lt, g.nx, g.ny, 1, max_label, out->volume,
+                                                   out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
+    }
+    if (out->hist32) {
+        st = hip_check(hipMemsetAsync(hist, 0, nlab * 32 * sizeof(uint32_t), s), "clear hist");
+        if (st) return st;
+        if (g.n > 0) {
+            ProfScope _p(ctx, s, "lt_histogram");
+            lt_histogram<L><<<(unsigned)((g.n + 255) / 256), 256, 0, s>>>(lab, lt, g.n, max_label,
+                                                                         out->max_lt_sq, hist);
+        }
+    }
+    {
+        ProfScope _p(ctx, s, "closed_forms");
+        closed_forms_kernel<<<lb, 256, 0, s>>>(out->volume, sq, out->max_lt_sq, out->shell_count, ssq,
+                                               (uint32_t)nlab, g.ndim, out->mean_lt, out->shell_mean_lt,
+                                               out->sphericity, out->roundness, hist, out->hist32);
+    }
+    return hip_check(hipGetLastError(), "measures launch");
+}
+
+lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                          const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
+                          hipStream_t s) {
+    switch (dt) {
+        case LT_U16: return measures_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, s);
+        case LT_I32: return measures_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, s);
+        case LT_U32: return measures_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, s);
+    }
+    return set_error(LT_E_DTYPE, "unknown dtype");
+}
+
+lt_status launch_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q, const int32_t* max_lt_sq,
+                              const uint64_t* shell_count, const uint64_t* shell_sum_q, uint32_t n,
+                              int ndim, float* mean_lt, float* shell_mean_lt, float* sphericity,
+                              float* roundness, hipStream_t s) {
+    closed_forms_kernel<<<(n + 255) / 256, 256, 0, s>>>(volume, sum_lt_q, max_lt_sq, shell_count,
+                                                        shell_sum_q, n, ndim, mean_lt, shell_mean_lt,
+                                                        sphericity, roundness, nullptr, nullptr);
+    return hip_check(hipGetLastError(), "closed forms launch");
+}
+
+}  // namespace lt

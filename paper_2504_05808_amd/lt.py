@@ -1,0 +1,243 @@
+"""Python binding of liblt (include/lt.h): argument marshalling only.
+
+Every step of the pipeline runs in the HIP library; this module only passes device
+pointers, shapes and the current torch stream across the C ABI.  PyTorch is used
+for device memory and streams.  If the built library is missing the binding raises
+at load time -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_liblt.so")
+
+LT_U16, LT_I32, LT_U32 = 1, 2, 3
+_DTYPES = {torch.uint16: LT_U16, torch.int32: LT_I32, torch.uint32: LT_U32}
+
+_lib = None
+
+
+class LTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"liblt status {status}: {message}")
+        self.status = status
+
+
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("total_ms", ctypes.c_double),
+                ("launches", ctypes.c_uint64)]
+
+
+class _Measures(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "volume", "shell_count", "max_lt_sq", "mean_lt", "shell_mean_lt", "sphericity",
+        "roundness", "hist32")]
+
+
+def load():
+    """Load the built HIP library (fails loudly if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"liblt is not built ({LIB_PATH} missing); run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, U32, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.lt_ctx_create.argtypes = [ctypes.POINTER(P), I]
+    lib.lt_ctx_destroy.argtypes = [P]
+    lib.lt_edt.argtypes = [P, P, I, I, i64p, P, V]
+    lib.lt_thickness.argtypes = [P, P, I, I, i64p, P, U32, P, V]
+    lib.lt_object_measures.argtypes = [P, P, I, I, i64p, P, U32, ctypes.POINTER(_Measures), V]
+    lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
+    lib.lt_sync_status.argtypes = [P, V]
+    lib.lt_profile_enable.argtypes = [P, I]
+    lib.lt_profile_read.argtypes = [P, ctypes.POINTER(_KernelTime), I, ctypes.POINTER(I)]
+    lib.lt_profile_reset.argtypes = [P]
+    lib.lt_status_str.argtypes = [I]
+    lib.lt_status_str.restype = ctypes.c_char_p
+    lib.lt_last_error.restype = ctypes.c_char_p
+    lib.lt_version.restype = ctypes.c_char_p
+    for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures",
+              "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
+              "lt_profile_reset"):
+        getattr(lib, f).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        lib = load()
+        raise LTError(status, f"{lib.lt_status_str(status).decode()}: {lib.lt_last_error().decode()}")
+
+
+def _shape(t: torch.Tensor):
+    arr = (ctypes.c_int64 * t.dim())(*t.shape)
+    return arr
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _labels(labels: torch.Tensor):
+    if labels.dtype not in _DTYPES:
+        raise TypeError(f"labels must be uint16, int32 or uint32 (got {labels.dtype})")
+    if labels.dim() not in (2, 3):
+        raise ValueError("labels must be 2D or 3D")
+    if not labels.is_cuda:
+        raise ValueError("labels must be a device tensor")
+    return labels.contiguous(), _DTYPES[labels.dtype]
+
+
+class Context:
+    """Owns a liblt context (scratch memory, tables, error word) on one device."""
+
+    def __init__(self, device: int | None = None):
+        self._lib = load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        _check(self._lib.lt_ctx_create(ctypes.byref(h), self.device))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lt_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_status(self, stream=None):
+        _check(self._lib.lt_sync_status(self._h, _stream(stream)))
+
+    def profile(self, on: bool = True):
+        _check(self._lib.lt_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(self._lib.lt_profile_reset(self._h))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} accumulated since the last reset."""
+        cap = 64
+        arr = (_KernelTime * cap)()
+        n = ctypes.c_int(0)
+        _check(self._lib.lt_profile_read(self._h, arr, cap, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].total_ms, int(arr[i].launches))
+                for i in range(min(n.value, cap))}
+
+
+_default_ctx: dict[int, Context] = {}
+
+
+def default_context() -> Context:
+    dev = torch.cuda.current_device()
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+def edt(labels: torch.Tensor, out: torch.Tensor | None = None, ctx: Context | None = None,
+        stream=None) -> torch.Tensor:
+    """Per-label squared EDT (int32), see lt_edt."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    out = out if out is not None else torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+    _check(ctx._lib.lt_edt(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), _ptr(out), _stream(stream)))
+    return out
+
+
+def thickness(labels: torch.Tensor, dist_sq: torch.Tensor, max_label: int,
+              out: torch.Tensor | None = None, ctx: Context | None = None, stream=None) -> torch.Tensor:
+    """Squared local thickness (int32), see lt_thickness."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    out = out if out is not None else torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+    _check(ctx._lib.lt_thickness(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab),
+                                 _ptr(dist_sq.contiguous()), int(max_label), _ptr(out), _stream(stream)))
+    return out
+
+
+@dataclass
+class Measures:
+    volume: torch.Tensor
+    shell_count: torch.Tensor
+    max_lt_sq: torch.Tensor
+    mean_lt: torch.Tensor
+    shell_mean_lt: torch.Tensor
+    sphericity: torch.Tensor
+    roundness: torch.Tensor
+    hist32: torch.Tensor | None = None
+
+
+def alloc_measures(n: int, device, hist: bool = False) -> Measures:
+    f = dict(device=device)
+    return Measures(
+        volume=torch.empty(n, dtype=torch.uint64, **f),
+        shell_count=torch.empty(n, dtype=torch.uint64, **f),
+        max_lt_sq=torch.empty(n, dtype=torch.int32, **f),
+        mean_lt=torch.empty(n, dtype=torch.float32, **f),
+        shell_mean_lt=torch.empty(n, dtype=torch.float32, **f),
+        sphericity=torch.empty(n, dtype=torch.float32, **f),
+        roundness=torch.empty(n, dtype=torch.float32, **f),
+        hist32=torch.empty((n, 32), dtype=torch.float32, **f) if hist else None)
+
+
+def object_measures(labels: torch.Tensor, lt_sq: torch.Tensor, max_label: int, hist: bool = False,
+                    out: Measures | None = None, ctx: Context | None = None, stream=None) -> Measures:
+    """Per-object measures (arrays indexed by label 0..max_label), see lt_object_measures."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    out = out or alloc_measures(int(max_label) + 1, lab.device, hist)
+    m = _Measures(*[_ptr(getattr(out, k)).value for k in (
+        "volume", "shell_count", "max_lt_sq", "mean_lt", "shell_mean_lt", "sphericity", "roundness",
+        "hist32")])
+    _check(ctx._lib.lt_object_measures(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab),
+                                       _ptr(lt_sq.contiguous()), int(max_label), ctypes.byref(m),
+                                       _stream(stream)))
+    return out
+
+
+def closed_forms(volume, sum_lt_q23, max_lt_sq, shell_count, shell_sum_q23, ndim: int,
+                 stream=None):
+    """Closed forms from per-object sums (device tensors), see lt_closed_forms."""
+    lib = load()
+    n = volume.numel()
+    dev = volume.device
+    outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4)]
+    _check(lib.lt_closed_forms(_ptr(volume), _ptr(sum_lt_q23), _ptr(max_lt_sq), _ptr(shell_count),
+                               _ptr(shell_sum_q23), n, ndim, *[_ptr(o) for o in outs], _stream(stream)))
+    return dict(zip(("mean_lt", "shell_mean_lt", "sphericity", "roundness"), outs))
+
+
+def measure(labels: torch.Tensor, max_label: int, hist: bool = False, ctx: Context | None = None,
+            stream=None):
+    """Whole pipeline: (dist_sq, lt_sq, Measures)."""
+    ctx = ctx or default_context()
+    d = edt(labels, ctx=ctx, stream=stream)
+    t = thickness(labels, d, max_label, ctx=ctx, stream=stream)
+    m = object_measures(labels, t, max_label, hist=hist, ctx=ctx, stream=stream)
+    return d, t, m
+
+
+def version() -> str:
+    return load().lt_version().decode()

@@ -1,0 +1,73 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+public header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2504_05808_amd import lt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lt.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lt.load()
+    names = _declared_functions()
+    assert "lt_edt" in names and "lt_thickness" in names and "lt_object_measures" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in lt.h but not exported"
+
+
+def test_status_strings_and_version():
+    lib = lt.load()
+    assert lib.lt_status_str(0) == b"ok"
+    assert lib.lt_status_str(6) == b"label out of range"
+    assert lib.lt_status_str(99) == b"unknown status"
+    assert b"gfx950" in lib.lt_version()
+
+
+def test_null_context_rejected():
+    lib = lt.load()
+    shape = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert lib.lt_edt(None, ctypes.c_void_p(8), lt.LT_U16, 3, shape, ctypes.c_void_p(8), None) == 1
+    assert lib.lt_thickness(None, None, lt.LT_U16, 3, shape, None, 5, None, None) == 1
+    assert lib.lt_sync_status(None, None) == 1
+    assert b"ctx" in lib.lt_last_error()
+
+
+def test_argument_errors_before_device_use():
+    """dtype and shape are validated before the context is dereferenced."""
+    lib = lt.load()
+    fake = ctypes.create_string_buffer(64)      # never dereferenced on these paths
+    ctx = ctypes.cast(fake, ctypes.c_void_p)
+    ok3 = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert lib.lt_edt(ctx, ctypes.c_void_p(8), 9, 3, ok3, ctypes.c_void_p(8), None) == 2
+    bad_nd = (ctypes.c_int64 * 4)(2, 2, 2, 2)
+    assert lib.lt_edt(ctx, ctypes.c_void_p(8), lt.LT_U16, 4, bad_nd, ctypes.c_void_p(8), None) == 3
+    neg = (ctypes.c_int64 * 3)(4, -1, 4)
+    assert lib.lt_edt(ctx, ctypes.c_void_p(8), lt.LT_U16, 3, neg, ctypes.c_void_p(8), None) == 3
+    big3 = (ctypes.c_int64 * 3)(1025, 8, 8)
+    assert lib.lt_edt(ctx, ctypes.c_void_p(8), lt.LT_I32, 3, big3, ctypes.c_void_p(8), None) == 3
+    big2 = (ctypes.c_int64 * 2)(8, 2049)
+    assert lib.lt_edt(ctx, ctypes.c_void_p(8), lt.LT_I32, 2, big2, ctypes.c_void_p(8), None) == 3
+    assert b"2048" in lib.lt_last_error()
+    assert lib.lt_edt(ctx, ctypes.c_void_p(8), lt.LT_U32, 3, None, ctypes.c_void_p(8), None) == 1
+    assert lib.lt_closed_forms(None, None, None, None, None, 4, 5, None, None, None, None, None) == 3
+    assert lib.lt_closed_forms(None, None, None, None, None, 0, 3, None, None, None, None, None) == 0
+    assert lib.lt_closed_forms(None, None, None, None, None, 4, 3, None, None, None, None, None) == 1
+
+
+def test_binding_rejects_host_and_bad_dtype_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        lt._labels(torch.zeros((4, 4), dtype=torch.float32))
+    with pytest.raises(ValueError):
+        lt._labels(torch.zeros((4, 4), dtype=torch.int32))

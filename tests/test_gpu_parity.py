@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Distances and local thickness are compared bit-exactly (integers); per-object
+volume, shell count and max LT exactly; the FP32 measures within 1e-5 relative
+of the FP64 oracle (the bound the method's FP32 outputs are held to; fixed-point
+radius sums contribute <= 2^-24 absolute per voxel and the FP32 closed forms a
+few ulp)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lt_oracle as O
+from paper_2504_05808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+FLOAT_KEYS = ("mean_lt", "shell_mean_lt", "sphericity", "roundness")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_05808_amd import lt
+    lt.load()
+    return torch, lt
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(gpu, lab, max_label=None, hist=False):
+    torch, lt = gpu
+    max_label = int(lab.max()) if max_label is None else max_label
+    t = torch.from_numpy(np.ascontiguousarray(lab)).cuda()
+    d, ltsq, m = lt.measure(t, max_label, hist=hist)
+    lt.default_context().sync_status()
+    out = dict(dist_sq=d.cpu().numpy().astype(np.int64), lt_sq=ltsq.cpu().numpy().astype(np.int64))
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        out[k] = getattr(m, k).cpu().numpy().astype(np.int64)
+    for k in FLOAT_KEYS:
+        out[k] = getattr(m, k).cpu().numpy().astype(np.float64)
+    if hist:
+        out["hist32"] = m.hist32.cpu().numpy().astype(np.float64)
+    return out
+
+
+def compare(got, ref, lab, fields=True):
+    if fields:
+        np.testing.assert_array_equal(got["dist_sq"], ref["dist_sq"])
+        np.testing.assert_array_equal(got["lt_sq"], ref["lt_sq"])
+    n = len(ref["volume"])
+    for k in ("volume", "shell_count"):
+        np.testing.assert_array_equal(got[k][:n], ref[k])
+    np.testing.assert_array_equal(got["max_lt_sq"][:n], ref["max_lt_sq"])
+    ok = ref["volume"] > 0
+    for k in FLOAT_KEYS:
+        g, r = got[k][:n], ref[k]
+        assert np.all(np.isnan(g[~ok]))
+        okk = ok & ~np.isnan(r)
+        np.testing.assert_allclose(g[okk], r[okk], rtol=RTOL, atol=0, err_msg=k)
+
+
+# ------------------------------------------------------------------ small random
+
+SHAPES = [(1, 1), (1, 37), (23, 1), (37, 70), (130, 67), (65, 129), (3, 5, 7), (9, 130, 67),
+          (17, 33, 65), (40, 9, 77), (1, 50, 60), (45, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("dtype", [np.uint16, np.int32, np.uint32])
+def test_random_labels_bit_exact(gpu, shape, dtype):
+    rng = synth.rng_for(1000 + len(shape) * 100 + shape[-1])
+    for blob, nl, pbg in [(1, 3, 0.3), (4, 5, 0.1), (8, 2, 0.0)]:
+        lab = synth.random_labels(rng, shape, n_labels=nl, p_bg=pbg, blob=blob, dtype=dtype)
+        _note(f"random shape={shape} dtype={np.dtype(dtype).name} blob={blob}")
+        ref = O.measure(lab, per_object=False)
+        got = run_gpu(gpu, lab)
+        compare(got, ref, lab)
+
+
+def test_cfg1_2d_ellipses(gpu):
+    lab, meta = synth.cfg1()
+    _note("cfg1 256x256 int32")
+    ref = O.measure(lab, per_object=False)
+    compare(run_gpu(gpu, lab), ref, lab)
+
+
+def test_cfg2_3d_ellipsoids_and_balls(gpu):
+    lab, meta = synth.cfg2()
+    _note("cfg2 128^3 int32")
+    ref = O.measure(lab)
+    got = run_gpu(gpu, lab)
+    compare(got, ref, lab)
+    for o in meta["objects"]:
+        if o["kind"] == "ball":
+            l, r = o["label"], o["r"]
+            assert np.all(got["lt_sq"][lab == l] == r * r + 1)
+            assert got["roundness"][l] == pytest.approx(1.0, abs=1e-6)
+
+
+def test_cfg3_sampled_objects(gpu):
+    """512^3 uint16 (the benchmark volume): per-object crops of 40 sampled labels
+    are checked bit-exactly; background must be zero everywhere."""
+    lab, meta = synth.cfg3()
+    _note(f"cfg3 512^3 uint16 objects={meta['n_objects']}")
+    max_label = int(lab.max())
+    got = run_gpu(gpu, lab, max_label)
+    assert np.all(got["lt_sq"][lab == 0] == 0) and np.all(got["dist_sq"][lab == 0] == 0)
+    rng = np.random.default_rng(5)
+    boxes = O.object_boxes(lab)
+    labels = sorted(boxes)
+    pick = rng.choice(labels, 40, replace=False)
+    big = max(labels, key=lambda l: np.prod([b - a for a, b in zip(*boxes[l])]))
+    pick = sorted(set(int(p) for p in pick) | {int(big)})
+    D, LT, _ = O.fields(lab, labels_subset=pick)
+    for l in pick:
+        sel = lab == l
+        np.testing.assert_array_equal(got["dist_sq"][sel], D[sel], err_msg=f"D label {l}")
+        np.testing.assert_array_equal(got["lt_sq"][sel], LT[sel], err_msg=f"LT label {l}")
+    # measures of the sampled objects from the oracle's fields
+    sub = np.where(np.isin(lab, pick), lab, 0)
+    sums = O.object_sums(sub, np.where(np.isin(lab, pick), LT, 0), max_label)
+    cf = O.closed_forms(sums, 3)
+    for l in pick:
+        assert got["volume"][l] == sums["volume"][l]
+        assert got["max_lt_sq"][l] == sums["max_lt_sq"][l]
+        for k in FLOAT_KEYS:
+            assert got[k][l] == pytest.approx(cf[k][l], rel=RTOL), (k, l)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_and_single_voxel(gpu):
+    for shape in [(8, 9), (5, 6, 7)]:
+        lab = np.zeros(shape, dtype=np.int32)
+        got = run_gpu(gpu, lab, max_label=3)
+        assert np.all(got["dist_sq"] == 0) and np.all(got["lt_sq"] == 0)
+        assert np.all(got["volume"] == 0) and np.all(np.isnan(got["sphericity"]))
+        lab.flat[len(lab.flat) // 2] = 2
+        ref = O.measure(lab, max_label=3, per_object=False)
+        compare(run_gpu(gpu, lab, max_label=3), ref, lab)
+
+
+def test_full_volume_one_label(gpu):
+    for shape in [(31, 47), (12, 20, 33)]:
+        lab = np.full(shape, 7, dtype=np.uint16)
+        ref = O.measure(lab, per_object=False)
+        compare(run_gpu(gpu, lab), ref, lab)
+
+
+def test_large_objects_span_tiles(gpu):
+    """Objects wider than one 32x64 paint tile and with large balls."""
+    m, _ = synth.disc_mask(60)
+    lab = np.zeros((140, 150), dtype=np.int32)
+    lab[5:5 + m.shape[0], 10:10 + m.shape[1]][m] = 1
+    lab[:, 140:] = 2
+    ref = O.measure(lab, per_object=False)
+    compare(run_gpu(gpu, lab), ref, lab)
+    lab3 = np.zeros((30, 90, 150), dtype=np.int32)
+    m3, off = synth.ellipsoid_mask((70.0, 40.0, 12.0), np.eye(3), (0.3, 0.1, 0.2))
+    o = np.array([15, 45, 75]) + off
+    lab3[o[0]:o[0] + m3.shape[0], o[1]:o[1] + m3.shape[1], o[2]:o[2] + m3.shape[2]][m3] = 1
+    lab3[:, 85:, :] = 3
+    ref3 = O.measure(lab3)
+    compare(run_gpu(gpu, lab3), ref3, lab3)
+
+
+def test_sparse_label_values_and_large_max_label(gpu):
+    rng = synth.rng_for(77)
+    lab = synth.random_labels(rng, (20, 30, 40), n_labels=4, blob=5, dtype=np.uint32)
+    lab = np.choose(lab, [0, 5, 60000, 70001, 3]).astype(np.uint32)
+    ref = O.measure(lab, max_label=80000, per_object=False)
+    compare(run_gpu(gpu, lab, max_label=80000), ref, lab)
+
+
+def test_histogram_bins(gpu):
+    lab, _ = synth.cfg2()
+    got = run_gpu(gpu, lab, hist=True)
+    ref = O.measure(lab)
+    h = O.lt_histogram(lab, ref["lt_sq"], ref["max_lt_sq"])
+    ok = ref["volume"] > 0
+    np.testing.assert_allclose(got["hist32"][ok], h[ok], rtol=1e-6, atol=1e-7)
+
+
+def test_label_above_max_label_sets_error(gpu):
+    torch, lt = gpu
+    lab = np.zeros((8, 8, 8), dtype=np.int32)
+    lab[2:5, 2:5, 2:5] = 9
+    t = torch.from_numpy(lab).cuda()
+    d = lt.edt(t)
+    x = lt.thickness(t, d, 4)
+    with pytest.raises(lt.LTError) as e:
+        lt.default_context().sync_status()
+    assert e.value.status == 6
+    lt.default_context().sync_status()          # the word was cleared
+
+
+def test_deterministic_repeat(gpu):
+    lab, _ = synth.cfg2()
+    a = run_gpu(gpu, lab)
+    b = run_gpu(gpu, lab)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_closed_forms_entry_fp32_vs_fp64(gpu):
+    """The FP32 closed forms over a wide range of volumes and mean thickness,
+    including near-spheres and extreme oblate / prolate spheroids."""
+    torch, lt = gpu
+    rng = np.random.default_rng(3)
+    n = 4000
+    V = np.concatenate([rng.integers(1, 10 ** 6, n - 8), [1, 7, 1000, 10 ** 6, 4169, 515, 2, 3]])
+    r0 = (3 * V / (4 * np.pi)) ** (1 / 3)
+    a = r0 * np.exp(rng.uniform(-2.5, 2.5, n))
+    a[:40] = r0[:40] * (1 + rng.uniform(-1e-3, 1e-3, 40))
+    a = np.maximum(a, 1.0)
+    q = np.rint(a * V * 2.0 ** 23).astype(np.uint64)
+    mx = np.rint(np.maximum(a, 1) ** 2 * 1.5).astype(np.int32)
+    ns = np.maximum(V // 3, 1).astype(np.uint64)
+    sq = np.rint(np.sqrt(mx * 0.8) * ns * 2.0 ** 23).astype(np.uint64)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    for ndim in (2, 3):
+        out = lt.closed_forms(dev(V.astype(np.uint64)), dev(q), dev(mx), dev(ns), dev(sq), ndim)
+        torch.cuda.synchronize()
+        mean = q.astype(np.float64) / 2.0 ** 23 / V
+        f = O.sphericity_3d if ndim == 3 else O.sphericity_2d
+        ref_s = np.array([f(float(v), float(m)) for v, m in zip(V, mean)])
+        ref_r = (sq.astype(np.float64) / 2.0 ** 23 / ns) / np.sqrt(mx.astype(np.float64))
+        np.testing.assert_allclose(out["sphericity"].cpu().numpy(), ref_s, rtol=RTOL)
+        np.testing.assert_allclose(out["roundness"].cpu().numpy(), ref_r, rtol=RTOL)
+        np.testing.assert_allclose(out["mean_lt"].cpu().numpy(), mean, rtol=RTOL)
