@@ -115,6 +115,8 @@ def main():
     t = torch.empty(vol.shape, dtype=torch.int32, device=dev)
     m = lt.alloc_measures(max_label + 1, dev)
 
+    print(f"# device {ctx.info()}", flush=True)
+
     def step():
         lt.edt(lab, out=d, ctx=ctx)
         lt.thickness(lab, d, max_label, out=t, ctx=ctx)
@@ -190,6 +192,7 @@ def main():
                          "frac": round(pipe_gbs / HBM_PEAK_GBS, 4),
                          "note": "36 B/voxel pass-structured algorithmic traffic / step time"},
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "device": ctx.info(),
         "kernel_ms": {k: round(v["avg_ms"], 4) for k, v in kernels.items()},
         "cpu_baseline": cpu,
     }

@@ -65,6 +65,10 @@ typedef struct lt_ctx lt_ctx;
 lt_status lt_ctx_create(lt_ctx** out, int device);
 /* Free the context's device memory (synchronises the device first). */
 lt_status lt_ctx_destroy(lt_ctx* ctx);
+/* Device facts the context planned with: compute units, LDS bytes per block and the
+ * row count of the local-thickness paint tiles (64 when the LDS allows, else 32).
+ * Any output pointer may be NULL. */
+lt_status lt_ctx_info(lt_ctx* ctx, int* n_cu, uint64_t* lds_per_block, int* paint_tile_rows);
 
 /* Per-label squared Euclidean distance transform (the distance map underlying the
  * local-thickness definition; Introduction and Method, first paragraph):

@@ -237,6 +237,14 @@ lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
                                mean_lt, shell_mean_lt, sphericity, roundness, (hipStream_t)stream);
 }
 
+lt_status lt_ctx_info(lt_ctx* ctx, int* n_cu, uint64_t* lds_per_block, int* paint_tile_rows_out) {
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    if (n_cu) *n_cu = ctx->n_cu;
+    if (lds_per_block) *lds_per_block = ctx->lds_per_block;
+    if (paint_tile_rows_out) *paint_tile_rows_out = paint_tile_rows(ctx);
+    return LT_OK;
+}
+
 lt_status lt_profile_enable(lt_ctx* ctx, int on) {
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     ctx->profile = on != 0;

@@ -16,36 +16,81 @@
 
 namespace lt {
 
+// Pass x: one block per row.  A wave takes 64 consecutive voxels; ballots give the
+// positions where a run starts (label differs from the left neighbour, or x = 0)
+// and ends.  A voxel's run [s, e] is found from the nearest start at or before it
+// and the nearest end at or after it -- in its own chunk via bit scans, otherwise
+// from the per-chunk extremes kept in LDS -- and g = min(x - s + 1, e - x + 1).
 template <typename L>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, uint32_t* err) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
+    __shared__ unsigned long long s_start[ROW_MAX_CHUNKS], s_end[ROW_MAX_CHUNKS];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int chunks = (nx + 63) >> 6;
     const size_t row = (size_t)blockIdx.z * ny + blockIdx.y;
     const L* r = lab + row * nx;
-    const L l = r[x];
-    int out = 0;
-    if (l != 0) {
-        if (label_negative(l)) atomicOr(err, ERR_LABEL);
-        int k = 1;
-        for (;; ++k) {
-            const int a = x - k, b = x + k;
-            if (a < 0 || b >= nx) break;
-            if (r[a] != l || r[b] != l) break;
+    for (int c = wid; c < chunks; c += nw) {
+        const int x = c * 64 + lane;
+        bool st = false, en = false;
+        if (x < nx) {
+            const L l = r[x];
+            if (label_negative(l)) atomicOr(err, ERR_LABEL);
+            st = x == 0 || r[x - 1] != l;
+            en = x == nx - 1 || r[x + 1] != l;
         }
-        out = k;
+        const unsigned long long ms = __ballot(st), me = __ballot(en);
+        if (lane == 0) {
+            s_start[c] = ms;
+            s_end[c] = me;
+        }
     }
-    g[row * nx + x] = (uint16_t)out;
+    __syncthreads();
+    for (int c = wid; c < chunks; c += nw) {
+        const int x = c * 64 + lane;
+        if (x >= nx) continue;
+        const L l = r[x];
+        int out = 0;
+        if (l != 0) {
+            const unsigned long long below = s_start[c] & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+            int s0;
+            if (below) {
+                s0 = c * 64 + 63 - __clzll(below);
+            } else {
+                int cc = c - 1;
+                while (s_start[cc] == 0ull) --cc;          // chunk 0 always has a start at x = 0
+                s0 = cc * 64 + 63 - __clzll(s_start[cc]);
+            }
+            const unsigned long long above = s_end[c] & ~((1ull << lane) - 1ull);
+            int e0;
+            if (above) {
+                e0 = c * 64 + __ffsll(above) - 1;
+            } else {
+                int cc = c + 1;
+                while (s_end[cc] == 0ull) ++cc;            // the last chunk ends at x = nx - 1
+                e0 = cc * 64 + __ffsll(s_end[cc]) - 1;
+            }
+            out = min(x - s0 + 1, e0 - x + 1);
+        }
+        g[row * nx + x] = (uint16_t)out;
+    }
 }
 
 // One line pass along y (AXIS = 1, input g, squared here) or z (AXIS = 2, input d2).
+// The outward search runs in steps of four: the labels and values of the next four
+// positions on each side are loaded together (independent loads), then consumed in
+// order until k^2 reaches the best value or the run ends.
+//
+// Blocks are 64 (x) x 8 (along the pass axis) voxels, so the rows a voxel's search
+// visits are mostly loaded by its own block and served from L1.
 template <typename L, int AXIS, typename F>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __restrict__ out,
               int nx, int ny, int nz) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
-    const int y = blockIdx.y, z = blockIdx.z;
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = AXIS == 1 ? blockIdx.y * 8 + threadIdx.y : blockIdx.y;
+    const int z = AXIS == 2 ? blockIdx.z * 8 + threadIdx.y : blockIdx.z;
+    if (x >= nx || y >= ny || z >= nz) return;
     const size_t i = ((size_t)z * ny + y) * nx + x;
     const L l = lab[i];
     if (l == 0) {
@@ -58,24 +103,39 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
     const int f0 = (int)f[i];
     int best = AXIS == 1 ? f0 * f0 : f0;
     bool lo = true, hi = true;
-    for (int k = 1; k * k < best && (lo || hi); ++k) {
-        const int kk = k * k;
-        if (lo) {
-            if (pos - k < 0 || lab[i - k * stride] != l) {
-                best = min(best, kk);
-                lo = false;
-            } else {
-                const int v = (int)f[i - k * stride];
-                best = min(best, kk + (AXIS == 1 ? v * v : v));
-            }
+    constexpr int U = 4;
+    for (int k0 = 1; k0 * k0 < best && (lo || hi); k0 += U) {
+        bool sa[U], sb[U];
+        int fa[U], fb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u;
+            const bool ina = pos - k >= 0, inb = pos + k < n;
+            sa[u] = ina ? lab[i - k * stride] == l : false;
+            sb[u] = inb ? lab[i + k * stride] == l : false;
+            fa[u] = ina ? (int)f[i - k * stride] : 0;
+            fb[u] = inb ? (int)f[i + k * stride] : 0;
         }
-        if (hi) {
-            if (pos + k >= n || lab[i + k * stride] != l) {
-                best = min(best, kk);
-                hi = false;
-            } else {
-                const int v = (int)f[i + k * stride];
-                best = min(best, kk + (AXIS == 1 ? v * v : v));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u, kk = k * k;
+            if (kk < best) {
+                if (lo) {
+                    if (!sa[u]) {
+                        best = min(best, kk);
+                        lo = false;
+                    } else {
+                        best = min(best, kk + (AXIS == 1 ? fa[u] * fa[u] : fa[u]));
+                    }
+                }
+                if (hi) {
+                    if (!sb[u]) {
+                        best = min(best, kk);
+                        hi = false;
+                    } else {
+                        best = min(best, kk + (AXIS == 1 ? fb[u] * fb[u] : fb[u]));
+                    }
+                }
             }
         }
     }
@@ -91,21 +151,25 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
     if (st) return st;
     uint16_t* gx = (uint16_t*)ctx->scratch.ptr;
     int32_t* d2 = (int32_t*)((char*)ctx->scratch.ptr + gbytes);
-    const dim3 block(256);
-    const dim3 grid((g.nx + 255) / 256, g.ny, g.nz);
-    { ProfScope _p(ctx, s, "edt_pass_x");
-    edt_pass_x<L><<<grid, block, 0, s>>>(lab, gx, g.nx, g.ny, ctx->d_err);
+    {
+        ProfScope _p(ctx, s, "edt_pass_x");
+        const int threads = min(1024, ((g.nx + 63) / 64) * 64);
+        edt_pass_x<L><<<dim3(1, g.ny, g.nz), threads, 0, s>>>(lab, gx, g.nx, g.ny, ctx->d_err);
     }
+    const dim3 lblock(64, 8);
+    const dim3 gy((g.nx + 63) / 64, (g.ny + 7) / 8, g.nz);
+    const dim3 gz((g.nx + 63) / 64, g.ny, (g.nz + 7) / 8);
     if (g.ndim == 2) {
-        { ProfScope _p(ctx, s, "edt_pass_y");
-        edt_pass_line<L, 1, uint16_t><<<grid, block, 0, s>>>(lab, gx, dist, g.nx, g.ny, g.nz);
-        }
+        ProfScope _p(ctx, s, "edt_pass_y");
+        edt_pass_line<L, 1, uint16_t><<<gy, lblock, 0, s>>>(lab, gx, dist, g.nx, g.ny, g.nz);
     } else {
-        { ProfScope _p(ctx, s, "edt_pass_y");
-        edt_pass_line<L, 1, uint16_t><<<grid, block, 0, s>>>(lab, gx, d2, g.nx, g.ny, g.nz);
+        {
+            ProfScope _p(ctx, s, "edt_pass_y");
+            edt_pass_line<L, 1, uint16_t><<<gy, lblock, 0, s>>>(lab, gx, d2, g.nx, g.ny, g.nz);
         }
-        { ProfScope _p(ctx, s, "edt_pass_z");
-        edt_pass_line<L, 2, int32_t><<<grid, block, 0, s>>>(lab, d2, dist, g.nx, g.ny, g.nz);
+        {
+            ProfScope _p(ctx, s, "edt_pass_z");
+            edt_pass_line<L, 2, int32_t><<<gz, lblock, 0, s>>>(lab, d2, dist, g.nx, g.ny, g.nz);
         }
     }
     return hip_check(hipGetLastError(), "edt launch");

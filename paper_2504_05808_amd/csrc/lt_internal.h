@@ -18,10 +18,18 @@ enum : uint32_t { ERR_LABEL = 1u, ERR_OVERFLOW = 2u };
 // with a larger D are kept without testing (always exact, only less pruning).
 constexpr int PRUNE_DCAP = 16384;
 
-// Paint tile: target rows x columns of one work item (columns along x).
-constexpr int TILE_Y = 32;
+// Paint tile: up to TILE_Y_MAX target rows x TILE_X columns per work item (columns
+// along x); the row count is 64 when a block may hold the 7-level table for 64 rows
+// in LDS (gfx950: 160 KB), else 32.  Rows are padded to TILE_STRIDE words so that
+// the lanes of a wave (one row each) fall in different LDS banks.
+constexpr int TILE_Y_MAX = 64;
 constexpr int TILE_X = 64;
+constexpr int TILE_STRIDE = TILE_X + 1;
 constexpr int TILE_LEVELS = 7;                 // interval lengths 1..64 -> levels 0..6
+constexpr int PAINT_THREADS = 1024;
+
+// Row scans (EDT pass x, bounding boxes): rows up to 2048 voxels = 32 wave chunks.
+constexpr int ROW_MAX_CHUNKS = 32;
 
 // Packed z-front entry (3D): bits 0..18 D of the centre, 19..28 dz + 512 (dz is
 // the slice minus the centre's z), 29..31 (plane 0 only) number of entries.
@@ -86,6 +94,7 @@ lt_status geom_from(int ndim, const int64_t* shape, Geom* g);
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                      int32_t* dist_sq, hipStream_t s);
 size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label);
+int paint_tile_rows(lt_ctx* ctx);
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
                            hipStream_t s);

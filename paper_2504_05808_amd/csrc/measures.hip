@@ -49,15 +49,17 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
             uint32_t max_label, uint64_t* __restrict__ vol, uint64_t* __restrict__ shc,
             int32_t* __restrict__ mx, uint64_t* __restrict__ sq, uint64_t* __restrict__ ssq,
             uint32_t* err) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
+    // blocks of 64 (x) x 4 (y): each wave is one row segment, and the rows above and
+    // below that the shell test reads are loaded by the same block
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y, z = blockIdx.z;
     const size_t plane = (size_t)ny * nx;
     const size_t i = (size_t)z * plane + (size_t)y * nx + x;
     uint64_t l = 0;
     int v = 0;
     bool shell = false;
     uint64_t q = 0;
-    if (x < nx) {
+    if (x < nx && y < ny) {
         const L raw = lab[i];
         if (raw != 0) {
             if (label_negative(raw) || (uint64_t)raw > max_label) {
@@ -84,7 +86,7 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
         const uint64_t s1 = wave_sum_u64(in ? q : 0);
         const uint64_t s2 = wave_sum_u64(in && shell ? q : 0);
         const int m1 = wave_max_i32(in ? v : 0);
-        if ((int)(threadIdx.x & 63) == lead) {
+        if ((int)threadIdx.x == lead) {
             atomicAdd((unsigned long long*)&vol[L0], (unsigned long long)__popcll(m));
             atomicAdd((unsigned long long*)&sq[L0], (unsigned long long)s1);
             atomicMax(&mx[L0], m1);
@@ -213,12 +215,12 @@ static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const 
     }
     if (g.n > 0) {
         ProfScope _p(ctx, s, "object_sums");
-        const dim3 grid((g.nx + 255) / 256, g.ny, g.nz);
+        const dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), blk(64, 4);
         if (g.ndim == 3)
-            object_sums<3, L><<<grid, 256, 0, s>>>(lab, lt, g.nx, g.ny, g.nz, max_label, out->volume,
+            object_sums<3, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, g.nz, max_label, out->volume,
                                                    out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
         else
-            object_sums<2, L><<<grid, 256, 0, s>>>(lab, lt, g.nx, g.ny, 1, max_label, out->volume,
+            object_sums<2, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, 1, max_label, out->volume,
                                                    out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
     }
     if (out->hist32) {

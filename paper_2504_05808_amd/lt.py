@@ -57,6 +57,7 @@ def load():
     lib.lt_object_measures.argtypes = [P, P, I, I, i64p, P, U32, ctypes.POINTER(_Measures), V]
     lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
     lib.lt_sync_status.argtypes = [P, V]
+    lib.lt_ctx_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I)]
     lib.lt_profile_enable.argtypes = [P, I]
     lib.lt_profile_read.argtypes = [P, ctypes.POINTER(_KernelTime), I, ctypes.POINTER(I)]
     lib.lt_profile_reset.argtypes = [P]
@@ -66,7 +67,7 @@ def load():
     lib.lt_version.restype = ctypes.c_char_p
     for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
-              "lt_profile_reset"):
+              "lt_profile_reset", "lt_ctx_info"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -129,6 +130,12 @@ class Context:
 
     def sync_status(self, stream=None):
         _check(self._lib.lt_sync_status(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        cu, tr = ctypes.c_int(0), ctypes.c_int(0)
+        lds = ctypes.c_uint64(0)
+        _check(self._lib.lt_ctx_info(self._h, ctypes.byref(cu), ctypes.byref(lds), ctypes.byref(tr)))
+        return {"n_cu": cu.value, "lds_per_block": lds.value, "paint_tile_rows": tr.value}
 
     def profile(self, on: bool = True):
         _check(self._lib.lt_profile_enable(self._h, 1 if on else 0))
