@@ -23,12 +23,13 @@ namespace lt {
 // from the per-chunk extremes kept in LDS -- and g = min(x - s + 1, e - x + 1).
 template <typename L>
 __global__ void __launch_bounds__(1024)
-edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, uint32_t* err) {
+edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, int nz, uint32_t* err) {
     __shared__ unsigned long long s_start[ROW_MAX_CHUNKS], s_end[ROW_MAX_CHUNKS];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     const int chunks = (nx + 63) >> 6;
-    const size_t row = (size_t)blockIdx.z * ny + blockIdx.y;
+  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
+    const size_t row = (size_t)z * ny + blockIdx.y;
     const L* r = lab + row * nx;
     for (int c = wid; c < chunks; c += nw) {
         const int x = c * 64 + lane;
@@ -74,72 +75,100 @@ edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, 
         }
         g[row * nx + x] = (uint16_t)out;
     }
+    __syncthreads();                                     // the masks are reused by the next row
+  }
 }
 
 // One line pass along y (AXIS = 1, input g, squared here) or z (AXIS = 2, input d2).
-// The outward search runs in steps of four: the labels and values of the next four
-// positions on each side are loaded together (independent loads), then consumed in
-// order until k^2 reaches the best value or the run ends.
-//
-// Blocks are 64 (x) x 8 (along the pass axis) voxels, so the rows a voxel's search
-// visits are mostly loaded by its own block and served from L1.
+// A block owns 64 consecutive x and LINE_T consecutive positions along the pass
+// axis; it stages labels and values of those positions plus LINE_H on each side in
+// LDS (coalesced row loads), and each voxel's outward search reads LDS.  A search
+// that runs past the staged range continues with global loads (exact either way).
+constexpr int LINE_T = 64, LINE_H = 32, LINE_ROWS = LINE_T + 2 * LINE_H;
+
 template <typename L, int AXIS, typename F>
 __global__ void __launch_bounds__(512)
 edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __restrict__ out,
               int nx, int ny, int nz) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = AXIS == 1 ? blockIdx.y * 8 + threadIdx.y : blockIdx.y;
-    const int z = AXIS == 2 ? blockIdx.z * 8 + threadIdx.y : blockIdx.z;
-    if (x >= nx || y >= ny || z >= nz) return;
-    const size_t i = ((size_t)z * ny + y) * nx + x;
-    const L l = lab[i];
-    if (l == 0) {
-        out[i] = 0;
-        return;
-    }
-    const ptrdiff_t stride = AXIS == 1 ? (ptrdiff_t)nx : (ptrdiff_t)nx * ny;
-    const int pos = AXIS == 1 ? y : z;
+    __shared__ L s_lab[LINE_ROWS * 64];
+    __shared__ int32_t s_val[LINE_ROWS * 64];
+    const int tx = threadIdx.x, ty = threadIdx.y;          // 64 x 8
+    const int x = blockIdx.x * 64 + tx;
     const int n = AXIS == 1 ? ny : nz;
-    const int f0 = (int)f[i];
-    int best = AXIS == 1 ? f0 * f0 : f0;
-    bool lo = true, hi = true;
-    constexpr int U = 4;
-    for (int k0 = 1; k0 * k0 < best && (lo || hi); k0 += U) {
-        bool sa[U], sb[U];
-        int fa[U], fb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u;
-            const bool ina = pos - k >= 0, inb = pos + k < n;
-            sa[u] = ina ? lab[i - k * stride] == l : false;
-            sb[u] = inb ? lab[i + k * stride] == l : false;
-            fa[u] = ina ? (int)f[i - k * stride] : 0;
-            fb[u] = inb ? (int)f[i + k * stride] : 0;
+    const int a0 = (AXIS == 1 ? blockIdx.y : blockIdx.z) * LINE_T;
+    const int o = AXIS == 1 ? blockIdx.z : blockIdx.y;     // the other coordinate
+    const ptrdiff_t stride = AXIS == 1 ? (ptrdiff_t)nx : (ptrdiff_t)nx * ny;
+    const size_t base = AXIS == 1 ? (size_t)o * ny * nx : (size_t)o * nx;   // (a = 0, x = 0)
+    const int lo = max(0, a0 - LINE_H), hi = min(n, a0 + LINE_T + LINE_H);
+    for (int r = ty; r < LINE_ROWS; r += 8) {
+        const int a = a0 - LINE_H + r;
+        L lv = L(0);
+        int fv = 0;
+        if (a >= lo && a < hi && x < nx) {
+            const size_t i = base + (size_t)a * stride + x;
+            lv = lab[i];
+            fv = (int)f[i];
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u, kk = k * k;
-            if (kk < best) {
-                if (lo) {
-                    if (!sa[u]) {
-                        best = min(best, kk);
-                        lo = false;
-                    } else {
-                        best = min(best, kk + (AXIS == 1 ? fa[u] * fa[u] : fa[u]));
-                    }
+        s_lab[r * 64 + tx] = lv;
+        s_val[r * 64 + tx] = AXIS == 1 ? fv * fv : fv;
+    }
+    __syncthreads();
+    if (x >= nx) return;
+    for (int r = LINE_H + ty; r < LINE_H + LINE_T; r += 8) {
+        const int p = a0 - LINE_H + r;
+        if (p >= n) break;
+        const L l = s_lab[r * 64 + tx];
+        const size_t i = base + (size_t)p * stride + x;
+        if (l == 0) {
+            out[i] = 0;
+            continue;
+        }
+        int best = s_val[r * 64 + tx];
+        bool dlo = true, dhi = true;
+        int k = 1;
+        for (; k * k < best && (dlo || dhi); ++k) {
+            if (r - k < 0 || r + k >= LINE_ROWS) break;           // leave the staged range
+            const int kk = k * k;
+            if (dlo) {
+                if (p - k < 0 || s_lab[(r - k) * 64 + tx] != l) {
+                    best = min(best, kk);
+                    dlo = false;
+                } else {
+                    best = min(best, kk + s_val[(r - k) * 64 + tx]);
                 }
-                if (hi) {
-                    if (!sb[u]) {
-                        best = min(best, kk);
-                        hi = false;
-                    } else {
-                        best = min(best, kk + (AXIS == 1 ? fb[u] * fb[u] : fb[u]));
-                    }
+            }
+            if (dhi) {
+                if (p + k >= n || s_lab[(r + k) * 64 + tx] != l) {
+                    best = min(best, kk);
+                    dhi = false;
+                } else {
+                    best = min(best, kk + s_val[(r + k) * 64 + tx]);
                 }
             }
         }
+        for (; k * k < best && (dlo || dhi); ++k) {                // beyond the halo
+            const int kk = k * k;
+            if (dlo) {
+                if (p - k < 0 || lab[i - k * stride] != l) {
+                    best = min(best, kk);
+                    dlo = false;
+                } else {
+                    const int v = (int)f[i - k * stride];
+                    best = min(best, kk + (AXIS == 1 ? v * v : v));
+                }
+            }
+            if (dhi) {
+                if (p + k >= n || lab[i + k * stride] != l) {
+                    best = min(best, kk);
+                    dhi = false;
+                } else {
+                    const int v = (int)f[i + k * stride];
+                    best = min(best, kk + (AXIS == 1 ? v * v : v));
+                }
+            }
+        }
+        out[i] = best;
     }
-    out[i] = best;
 }
 
 template <typename L>
@@ -154,11 +183,13 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
     {
         ProfScope _p(ctx, s, "edt_pass_x");
         const int threads = min(1024, ((g.nx + 63) / 64) * 64);
-        edt_pass_x<L><<<dim3(1, g.ny, g.nz), threads, 0, s>>>(lab, gx, g.nx, g.ny, ctx->d_err);
+        const int gz = loop_extent(g.nz, g.ny, ctx);
+        edt_pass_x<L><<<dim3(1, g.ny, gz), threads, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err);
     }
     const dim3 lblock(64, 8);
-    const dim3 gy((g.nx + 63) / 64, (g.ny + 7) / 8, g.nz);
-    const dim3 gz((g.nx + 63) / 64, g.ny, (g.nz + 7) / 8);
+    const int bx = (g.nx + 63) / 64;
+    const dim3 gy(bx, (g.ny + LINE_T - 1) / LINE_T, g.nz);
+    const dim3 gz(bx, g.ny, (g.nz + LINE_T - 1) / LINE_T);
     if (g.ndim == 2) {
         ProfScope _p(ctx, s, "edt_pass_y");
         edt_pass_line<L, 1, uint16_t><<<gy, lblock, 0, s>>>(lab, gx, dist, g.nx, g.ny, g.nz);

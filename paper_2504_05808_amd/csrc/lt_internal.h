@@ -32,13 +32,14 @@ constexpr int PAINT_THREADS = 1024;
 constexpr int ROW_MAX_CHUNKS = 32;
 
 // Packed z-front entry (3D): bits 0..18 D of the centre, 19..28 dz + 512 (dz is
-// the slice minus the centre's z), 29..31 (plane 0 only) number of entries.
+// the slice minus the centre's z), 29..31 (plane 0 only) number of entries, 7 =
+// more than ZF_PLANES (the column is rescanned).
 constexpr uint32_t ZF_D_BITS = 19;
 constexpr uint32_t ZF_D_MASK = (1u << ZF_D_BITS) - 1u;
 constexpr uint32_t ZF_DZ_SHIFT = 19;
 constexpr uint32_t ZF_DZ_MASK = 1023u;
 constexpr uint32_t ZF_N_SHIFT = 29;
-constexpr int ZF_PLANES = 3;
+constexpr int ZF_PLANES = 4;
 
 // Column-list entry (3D): (D << 11) | z.
 constexpr uint32_t CL_Z_BITS = 11;
@@ -129,6 +130,15 @@ struct ProfScope {
         }
     }
 };
+
+// Grid extent along a looped dimension: enough blocks to fill the device about
+// `per_cu` times over (each block then loops), never more than the dimension.
+inline int loop_extent(int n_outer, long other_blocks, const lt_ctx* ctx, int per_cu = 16) {
+    const long target = (long)ctx->n_cu * per_cu;
+    long g = (target + other_blocks - 1) / (other_blocks > 0 ? other_blocks : 1);
+    if (g > n_outer) g = n_outer;
+    return g < 1 ? 1 : (int)g;
+}
 
 // Fixed-point scale of the deterministic radius sums (Q.23 in uint64).
 constexpr double SUM_SCALE = 8388608.0;

@@ -52,8 +52,9 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
     // blocks of 64 (x) x 4 (y): each wave is one row segment, and the rows above and
     // below that the shell test reads are loaded by the same block
     const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y, z = blockIdx.z;
+    const int y = blockIdx.y * 4 + threadIdx.y;
     const size_t plane = (size_t)ny * nx;
+  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
     const size_t i = (size_t)z * plane + (size_t)y * nx + x;
     uint64_t l = 0;
     int v = 0;
@@ -97,6 +98,7 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
         }
         active &= ~m;
     }
+  }
 }
 
 // Local-thickness histogram (32 bins of sqrt(LT_sq) / R, R^2 = the object's max):
@@ -215,7 +217,8 @@ static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const 
     }
     if (g.n > 0) {
         ProfScope _p(ctx, s, "object_sums");
-        const dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), blk(64, 4);
+        const long b2 = (long)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+        const dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, loop_extent(g.nz, b2, ctx, 1 << 20)), blk(64, 4);
         if (g.ndim == 3)
             object_sums<3, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, g.nz, max_label, out->volume,
                                                    out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);

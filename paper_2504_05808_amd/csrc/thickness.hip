@@ -50,13 +50,14 @@ __global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uin
 // label.  bb layout: [zmin, zmax, ymin, ymax, xmin, xmax][nlab].
 template <typename L>
 __global__ void __launch_bounds__(1024)
-bbox_runs(const L* __restrict__ lab, int nx, int ny, uint32_t max_label, int32_t* bb,
+bbox_runs(const L* __restrict__ lab, int nx, int ny, int nz, uint32_t max_label, int32_t* bb,
           uint32_t nlab, uint32_t* err) {
     __shared__ unsigned long long s_end[ROW_MAX_CHUNKS];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     const int chunks = (nx + 63) >> 6;
-    const int y = blockIdx.y, z = blockIdx.z;
+    const int y = blockIdx.y;
+  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
     const L* r = lab + ((size_t)z * ny + y) * nx;
     for (int c = wid; c < chunks; c += nw) {
         const int x = c * 64 + lane;
@@ -92,6 +93,8 @@ bbox_runs(const L* __restrict__ lab, int nx, int ny, uint32_t max_label, int32_t
         atomicMin(&bb[4 * nlab + u], x);
         atomicMax(&bb[5 * nlab + u], e);
     }
+    __syncthreads();                                     // the masks are reused by the next row
+  }
 }
 
 // ------------------------------------------------------------------ Pareto fronts
@@ -181,9 +184,9 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         int32_t* __restrict__ lt, int32_t* __restrict__ maxd, uint32_t* err) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
     const bool inside = x < nx && y < ny;
     const size_t plane = (size_t)ny * nx;
+  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
     const size_t i = inside ? (size_t)z * plane + (size_t)y * nx + x : 0;
     const int d = inside ? D[i] : 0;
     bool keep = false;
@@ -216,6 +219,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         if (d <= 0) lt[i] = 0;
     }
     wave_label_max(l, keep, d, maxd);
+  }
 }
 
 // ------------------------------------------------------------------ 3D z-fronts
@@ -281,21 +285,24 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, const uint32_t*
             if (b > 0) front_insert(f, v, b, dz);
         }
         int m = 0;
-        uint32_t p[ZF_PLANES] = {0u, 0u, 0u};
+        uint32_t p[ZF_PLANES];
+#pragma unroll
+        for (int k = 0; k < ZF_PLANES; ++k) p[k] = 0u;
 #pragma unroll
         for (int k = 0; k < ZF_PLANES; ++k)
             if (f.v[k] != 0) {
                 const uint32_t w = zf_pack(f.v[k], f.dz[k]);
-                if (m == 0) p[0] = w;
-                else if (m == 1) p[1] = w;
-                else p[2] = w;
+#pragma unroll
+                for (int q = 0; q < ZF_PLANES; ++q)
+                    if (q == m) p[q] = w;
                 ++m;
             }
         const size_t i = (size_t)z * plane + col;
         const uint32_t nfield = f.overflow ? 7u : (uint32_t)m;
         zf[i] = m ? (p[0] | (nfield << ZF_N_SHIFT)) : 0u;
-        if (m >= 2) zf[n + i] = p[1];
-        if (m >= 3) zf[2 * n + i] = p[2];
+#pragma unroll
+        for (int q = 1; q < ZF_PLANES; ++q)
+            if (m > q) zf[q * n + i] = p[q];
     }
 }
 
@@ -526,7 +533,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     }
                     const bool own = sx < sx1 && (uint64_t)lc == (uint64_t)l;
                     const uint32_t e0 = own ? ec : 0u;
-                    uint32_t e1 = 0u, e2 = 0u;
+                    uint32_t e[ZF_PLANES];
+                    e[0] = e0;
+#pragma unroll
+                    for (int q = 1; q < ZF_PLANES; ++q) e[q] = 0u;
                     int nent = 0;
                     bool ovf = false;
                     if (NDIM == 2) {
@@ -534,23 +544,24 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     } else if (e0) {
                         const int cc = (int)(e0 >> ZF_N_SHIFT);
                         ovf = cc == 7;
-                        nent = ovf ? 3 : cc;
-                        if (nent >= 2) e1 = zf[n + rowi + sx];
-                        if (nent >= 3) e2 = zf[2 * n + rowi + sx];
+                        nent = ovf ? 0 : cc;
+#pragma unroll
+                        for (int q = 1; q < ZF_PLANES; ++q)
+                            if (nent > q) e[q] = zf[q * n + rowi + sx];
                     }
                     // stored front entries, one disc per lane per pass
-                    for (int p = 0; p < 3; ++p) {
-                        const bool has = !ovf && p < nent;
+#pragma unroll
+                    for (int p = 0; p < ZF_PLANES; ++p) {
+                        const bool has = p < nent;
                         const uint64_t mask = __ballot(has);
                         if (!mask) break;
                         int v = 0, b = 0;
                         if (has) {
-                            const uint32_t e = p == 0 ? e0 : (p == 1 ? e1 : e2);
                             if (NDIM == 2) {
-                                v = b = (int)(e & 0x7fffffffu);
+                                v = b = (int)(e[p] & 0x7fffffffu);
                             } else {
-                                v = (int)(e & ZF_D_MASK);
-                                const int dz = (int)((e >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
+                                v = (int)(e[p] & ZF_D_MASK);
+                                const int dz = (int)((e[p] >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
                                 b = v - dz * dz;
                             }
                         }
@@ -558,27 +569,26 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     }
                     // fronts larger than the planes: every kept centre of the column
                     // (within the object's z range) that reaches this slice -- a superset
-                    // of the front -- one per pass
+                    // of the front.  The wave walks the offsets dz = -R..R together, four
+                    // independent loads at a time, and paints each offset's discs.
                     if (NDIM == 3 && __ballot(ovf)) {
-                        int zc = ovf ? max(z0, pz - R) : 1, zend = ovf ? min(z1 - 1, pz + R) : 0;
                         const size_t col = (size_t)sy * nx + sx;
-                        for (;;) {
-                            bool has = false;
-                            int v = 0, b = 0;
-                            while (zc <= zend) {
-                                const int vv = kd[(size_t)zc * ((size_t)nx * ny) + col];
-                                const int dz = pz - zc;
-                                ++zc;
-                                if (vv - dz * dz > 0) {
-                                    v = vv;
-                                    b = vv - dz * dz;
-                                    has = true;
-                                    break;
-                                }
+                        const size_t pl = (size_t)nx * ny;
+                        for (int d0 = -R; d0 <= R; d0 += 4) {
+                            int kv[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int zc = pz + d0 + u;
+                                kv[u] = (ovf && d0 + u <= R && zc >= z0 && zc < z1) ? kd[(size_t)zc * pl + col] : 0;
                             }
-                            const uint64_t mask = __ballot(has);
-                            if (!mask) break;
-                            paint_mask(t, mask, v, b, sx, sy, lane);
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int dz = d0 + u;
+                                const int b = kv[u] - dz * dz;
+                                const bool has = kv[u] > 0 && b > 0;
+                                const uint64_t mask = __ballot(has);
+                                if (mask) paint_mask(t, mask, kv[u], b, sx, sy, lane);
+                            }
                         }
                     }
                 }
@@ -682,14 +692,15 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     {
         ProfScope _p(ctx, s, "bbox_runs");
         const int threads = min(1024, ((g.nx + 63) / 64) * 64);
-        bbox_runs<L><<<dim3(1, g.ny, g.nz), threads, 0, s>>>(lab, g.nx, g.ny, max_label, bb, nlab,
-                                                             ctx->d_err);
+        bbox_runs<L><<<dim3(1, g.ny, loop_extent(g.nz, g.ny, ctx)), threads, 0, s>>>(
+            lab, g.nx, g.ny, g.nz, max_label, bb, nlab, ctx->d_err);
     }
     if (g.ndim == 3) {
         const dim3 b2(64, 4);
         {
             ProfScope _p(ctx, s, "prune3d");
-            prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), b2, 0, s>>>(
+            const long pb = (long)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+            prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, loop_extent(g.nz, pb, ctx)), b2, 0, s>>>(
                 lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd, lt, maxd, ctx->d_err);
         }
         {
