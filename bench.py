@@ -81,6 +81,72 @@ def cpu_baseline(vol: np.ndarray, seconds: float, threads: int) -> dict:
     }
 
 
+def batch_bench(args):
+    """Batched form vs plain per-volume launches on the same GPU (reduced batch:
+    64 cubes with edges U{64..160} and U{5..60} objects each, same shape recipe as
+    the 512^3 volume)."""
+    import torch
+
+    from paper_2504_05808_amd import lt, synth
+
+    n = args.batch_volumes
+    kw = dict(n_volumes=n, edges=(64, 160), counts=(5, 60))
+    t0 = time.perf_counter()
+    vols = [synth.cfg4_volume(i, **kw)[0] for i in range(n)]
+    print(f"# batch of {n} volumes generated in {time.perf_counter() - t0:.1f}s", flush=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = lt.default_context()
+    labs = [torch.from_numpy(v).to(dev) for v in vols]
+    mls = [int(v.max()) for v in vols]
+    vox = sum(v.size for v in vols)
+    objs = sum(mls)
+    b = lt.Batch(list(zip(labs, mls)), ctx=ctx,
+                 autotune_cache=os.environ.get("LT_AUTOTUNE_CACHE"), autotune_repeats=2)
+    plain_out = [(torch.empty(l.shape, dtype=torch.int32, device=dev),
+                  torch.empty(l.shape, dtype=torch.int32, device=dev),
+                  lt.alloc_measures(ml + 1, dev)) for l, ml in zip(labs, mls)]
+
+    def plain():
+        for l, ml, (d, t, m) in zip(labs, mls, plain_out):
+            lt.edt(l, out=d, ctx=ctx)
+            lt.thickness(l, d, ml, out=t, ctx=ctx)
+            lt.object_measures(l, t, ml, out=m, ctx=ctx)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        t_host = time.perf_counter()
+        a.record()
+        for _ in range(args.steps):
+            fn()
+        z.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / args.steps, (time.perf_counter() - t_host) * 1e3 / args.steps
+
+    ms_plain, host_plain = timed(plain)
+    ms_graph, host_graph = timed(b.run)
+    ctx.sync_status()
+    same = all(torch.equal(p[1], q[1]) for p, q in zip(plain_out, b.outputs))
+    print(json.dumps({
+        "metric": "batched volumes: voxels/s, one graph launch vs per-volume plain launches",
+        "value": vox / (ms_graph * 1e-3), "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"{n} uint16 cubes, edges 64-160, 5-60 objects each", "voxels": vox,
+                   "objects": objs},
+        "plain": {"ms_per_step": ms_plain, "host_ms_per_step": host_plain,
+                  "voxels_per_s": vox / (ms_plain * 1e-3)},
+        "graph": {"ms_per_step": ms_graph, "host_ms_per_step": host_graph,
+                  "objects_per_s": objs / (ms_graph * 1e-3)},
+        "speedup": ms_plain / ms_graph, "identical_lt": bool(same), "tuning": ctx.get_tuning(),
+    }), flush=True)
+    b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,11 +154,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="measure the batched graph form against per-volume launches instead")
+    ap.add_argument("--batch-volumes", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
               "independent objects but no multi-GPU run is part of this build.", file=sys.stderr)
         sys.exit(2)
+    if args.batch:
+        batch_bench(args)
+        return
 
     import torch
 

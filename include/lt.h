@@ -138,6 +138,59 @@ lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
  * Returns LT_OK, LT_E_LABEL_RANGE, LT_E_OVERFLOW or LT_E_HIP. */
 lt_status lt_sync_status(lt_ctx* ctx, void* stream);
 
+/* ---------------------------------------------------------------- batched form
+ * Many volumes of uneven size (one label dtype) processed by one graph launch.
+ * Every volume gets the full pipeline (lt_edt, lt_thickness, lt_object_measures)
+ * with the same outputs and bit-identical results as the plain calls.  The
+ * volumes are spread over `batch_lanes` concurrent streams (lt_tuning), largest
+ * first; the whole batch is captured once into a hipGraph that lt_batch_run
+ * replays with a single hipGraphLaunch on `stream`.  The batch owns its scratch
+ * (one region per lane); the caller keeps every volume's buffers alive and at the
+ * same addresses for the life of the batch.  Replays of one batch must not overlap. */
+typedef struct {
+    const void* labels;       /* device, `dtype` of the batch */
+    int ndim;                 /* 2 or 3 */
+    int64_t shape[3];         /* {nz, ny, nx} or {ny, nx, -} */
+    uint32_t max_label;
+    int32_t* dist_sq;         /* device outputs as in lt_edt / lt_thickness */
+    int32_t* lt_sq;
+    lt_measures measures;     /* device outputs as in lt_object_measures */
+} lt_volume;
+typedef struct lt_batch lt_batch;
+lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n_volumes, lt_dtype dtype,
+                          lt_batch** out);
+lt_status lt_batch_run(lt_batch* batch, void* stream);
+lt_status lt_batch_destroy(lt_batch* batch);
+
+/* ---------------------------------------------------------------- tuning
+ * Runtime kernel knobs.  paint_tile_rows: 32 or 64 rows per local-thickness paint
+ * tile (0 = 64 when the LDS allows); paint_blocks_per_cu: 1 or 2 persistent paint
+ * blocks per compute unit (2 only takes effect with 32-row tiles); front_chunk: 32,
+ * 64 or 128 slices per thread in the z-front pass; batch_lanes: 1..16 streams in a
+ * batch graph.  Results never depend on the knobs, only the speed does. */
+typedef struct {
+    int paint_tile_rows;
+    int paint_blocks_per_cu;
+    int front_chunk;
+    int batch_lanes;
+} lt_tuning;
+lt_status lt_get_tuning(lt_ctx* ctx, lt_tuning* out);
+lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* tuning);
+
+/* Autotuner.  lt_autotune times the full pipeline on the given volume (device
+ * labels) for every combination of paint tile rows, paint blocks per CU and
+ * z-front chunk (`repeats` timed runs each after one warm-up), sets the fastest on
+ * the context and returns it in *best (may be NULL).  lt_autotune_batch does the
+ * same for batch_lanes on a batch.  Winners are cached in the JSON file
+ * `cache_path` (NULL: no cache) under a key of device architecture, dtype,
+ * dimensionality and size class; a cached key is applied without timing.  The
+ * tuner allocates temporary device memory and synchronises the device. */
+lt_status lt_autotune(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                      const int64_t* shape, uint32_t max_label, const char* cache_path,
+                      int repeats, lt_tuning* best);
+lt_status lt_autotune_batch(lt_ctx* ctx, const lt_volume* vols, int n_volumes, lt_dtype dtype,
+                            const char* cache_path, int repeats, lt_tuning* best);
+
 /* Kernel timing (tracing).  When enabled, every kernel the library launches is
  * bracketed by two HIP events recorded on the launch stream; lt_profile_read waits
  * for the pending events and returns per-kernel totals accumulated since the last

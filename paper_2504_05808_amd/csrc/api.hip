@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -43,6 +44,13 @@ lt_status ensure_scratch(lt_ctx* ctx, size_t bytes) {
     ctx->scratch.ptr = p;
     ctx->scratch.bytes = want;
     return LT_OK;
+}
+
+size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label) {
+    size_t b = edt_scratch_bytes(g);
+    b = std::max(b, thickness_scratch_bytes(g, max_label));
+    b = std::max(b, measures_scratch_bytes(max_label));
+    return (b + 255) & ~size_t(255);
 }
 
 lt_status geom_from(int ndim, const int64_t* shape, Geom* g) {
@@ -194,7 +202,8 @@ lt_status lt_edt(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, cons
     if (st) return st;
     if (g.n == 0) return LT_OK;
     if (!dist_sq) return set_error(LT_E_ARG, "dist_sq is NULL");
-    return launch_edt(ctx, labels, dtype, g, dist_sq, (hipStream_t)stream);
+    if ((st = ensure_scratch(ctx, edt_scratch_bytes(g)))) return st;
+    return launch_edt(ctx, labels, dtype, g, dist_sq, ctx->scratch.ptr, (hipStream_t)stream);
 }
 
 lt_status lt_thickness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
@@ -206,7 +215,9 @@ lt_status lt_thickness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim
     if (g.n == 0) return LT_OK;
     if (!dist_sq || !lt_sq) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
     if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
-    return launch_thickness(ctx, labels, dtype, g, dist_sq, max_label, lt_sq, (hipStream_t)stream);
+    if ((st = ensure_scratch(ctx, thickness_scratch_bytes(g, max_label)))) return st;
+    return launch_thickness(ctx, labels, dtype, g, dist_sq, max_label, lt_sq, ctx->scratch.ptr,
+                            (hipStream_t)stream);
 }
 
 lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
@@ -220,7 +231,9 @@ lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, in
         return set_error(LT_E_ARG, "an output array of lt_measures is NULL");
     if (g.n > 0 && !lt_sq) return set_error(LT_E_ARG, "lt_sq is NULL");
     if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
-    return launch_measures(ctx, labels, dtype, g, lt_sq, max_label, out, (hipStream_t)stream);
+    if ((st = ensure_scratch(ctx, measures_scratch_bytes(max_label)))) return st;
+    return launch_measures(ctx, labels, dtype, g, lt_sq, max_label, out, ctx->scratch.ptr,
+                           (hipStream_t)stream);
 }
 
 lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,

@@ -171,15 +171,18 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
     }
 }
 
+size_t edt_scratch_bytes(const Geom& g) {
+    const size_t gbytes = (g.n * sizeof(uint16_t) + 255) & ~size_t(255);
+    return gbytes + (g.ndim == 3 ? g.n * sizeof(int32_t) : 0);
+}
+
 template <typename L>
-static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* dist, hipStream_t s) {
+static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* dist, void* scratch,
+                           hipStream_t s) {
     // scratch: g (uint16) then d2 (int32, 3D only)
     const size_t gbytes = (g.n * sizeof(uint16_t) + 255) & ~size_t(255);
-    const size_t need = gbytes + (g.ndim == 3 ? g.n * sizeof(int32_t) : 0);
-    lt_status st = ensure_scratch(ctx, need);
-    if (st) return st;
-    uint16_t* gx = (uint16_t*)ctx->scratch.ptr;
-    int32_t* d2 = (int32_t*)((char*)ctx->scratch.ptr + gbytes);
+    uint16_t* gx = (uint16_t*)scratch;
+    int32_t* d2 = (int32_t*)((char*)scratch + gbytes);
     {
         ProfScope _p(ctx, s, "edt_pass_x");
         const int threads = min(1024, ((g.nx + 63) / 64) * 64);
@@ -207,11 +210,11 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
 }
 
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, int32_t* dist_sq,
-                     hipStream_t s) {
+                     void* scratch, hipStream_t s) {
     switch (dt) {
-        case LT_U16: return edt_typed(ctx, (const uint16_t*)labels, g, dist_sq, s);
-        case LT_I32: return edt_typed(ctx, (const int32_t*)labels, g, dist_sq, s);
-        case LT_U32: return edt_typed(ctx, (const uint32_t*)labels, g, dist_sq, s);
+        case LT_U16: return edt_typed(ctx, (const uint16_t*)labels, g, dist_sq, scratch, s);
+        case LT_I32: return edt_typed(ctx, (const int32_t*)labels, g, dist_sq, scratch, s);
+        case LT_U32: return edt_typed(ctx, (const uint32_t*)labels, g, dist_sq, scratch, s);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

@@ -56,6 +56,14 @@ struct Scratch {
     size_t bytes = 0;
 };
 
+// Runtime kernel knobs (chosen by the autotuner or set by the caller; 0 = default).
+struct Tuning {
+    int paint_tile_rows = 0;      // 32 or 64 rows per paint tile (0: 64 when LDS allows)
+    int paint_blocks_per_cu = 1;  // persistent paint blocks per compute unit (1 or 2)
+    int front_chunk = 64;         // slices per thread in the z-front pass (32, 64 or 128)
+    int batch_lanes = 4;          // concurrent streams in a captured batch graph
+};
+
 // One timed launch: events recorded on the launch stream around the kernel.
 struct PendingTiming {
     const char* name;
@@ -78,6 +86,7 @@ struct lt_ctx {
     int32_t* d_prune3 = nullptr;        // [3][PRUNE_DCAP + 1] (|o|^2 = 1, 2, 3)
     int32_t* d_prune2 = nullptr;        // [2][PRUNE_DCAP + 1] (|o|^2 = 1, 2)
     lt::Scratch scratch;                // grows on demand, freed by lt_ctx_destroy
+    lt::Tuning tune;
     bool profile = false;               // time every launch with HIP events
     std::vector<lt::PendingTiming> pending;
     std::vector<lt::KernelTotal> totals;
@@ -91,18 +100,23 @@ lt_status hip_check(hipError_t e, const char* what);
 lt_status ensure_scratch(lt_ctx* ctx, size_t bytes);
 lt_status geom_from(int ndim, const int64_t* shape, Geom* g);
 
-// Launchers (edt.hip, thickness.hip, measures.hip).  All are stream-ordered.
+// Launchers (edt.hip, thickness.hip, measures.hip).  All are stream-ordered, use the
+// caller's scratch region (at least *_scratch_bytes bytes, 256-byte aligned) and
+// allocate nothing, so they can be captured into a graph.
+size_t edt_scratch_bytes(const Geom& g);
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
-                     int32_t* dist_sq, hipStream_t s);
+                     int32_t* dist_sq, void* scratch, hipStream_t s);
 size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label);
 int paint_tile_rows(lt_ctx* ctx);
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           hipStream_t s);
+                           void* scratch, hipStream_t s);
 size_t measures_scratch_bytes(uint32_t max_label);
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                           const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
-                          hipStream_t s);
+                          void* scratch, hipStream_t s);
+// Scratch for a whole pipeline (EDT, thickness, measures run in turn).
+size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label);
 lt_status launch_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q,
                               const int32_t* max_lt_sq, const uint64_t* shell_count,
                               const uint64_t* shell_sum_q, uint32_t n, int ndim,

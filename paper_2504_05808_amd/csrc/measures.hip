@@ -199,13 +199,17 @@ size_t measures_scratch_bytes(uint32_t max_label) {
     return 2 * align256(nlab * sizeof(uint64_t)) + align256(nlab * 32 * sizeof(uint32_t));
 }
 
+__global__ void fill_u32(uint32_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 template <typename L>
 static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
-                                uint32_t max_label, const lt_measures* out, hipStream_t s) {
+                                uint32_t max_label, const lt_measures* out, void* scratch,
+                                hipStream_t s) {
     const size_t nlab = (size_t)max_label + 1;
-    lt_status st = ensure_scratch(ctx, measures_scratch_bytes(max_label));
-    if (st) return st;
-    char* base = (char*)ctx->scratch.ptr;
+    char* base = (char*)scratch;
     uint64_t* sq = (uint64_t*)base;
     uint64_t* ssq = (uint64_t*)(base + align256(nlab * sizeof(uint64_t)));
     uint32_t* hist = (uint32_t*)(base + 2 * align256(nlab * sizeof(uint64_t)));
@@ -227,8 +231,10 @@ static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const 
                                                    out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
     }
     if (out->hist32) {
-        st = hip_check(hipMemsetAsync(hist, 0, nlab * 32 * sizeof(uint32_t), s), "clear hist");
-        if (st) return st;
+        {
+            ProfScope _p(ctx, s, "fill_u32");
+            fill_u32<<<(unsigned)min((size_t)4096, (nlab * 32 + 255) / 256), 256, 0, s>>>(hist, nlab * 32);
+        }
         if (g.n > 0) {
             ProfScope _p(ctx, s, "lt_histogram");
             lt_histogram<L><<<(unsigned)((g.n + 255) / 256), 256, 0, s>>>(lab, lt, g.n, max_label,
@@ -246,11 +252,11 @@ static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const 
 
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                           const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
-                          hipStream_t s) {
+                          void* scratch, hipStream_t s) {
     switch (dt) {
-        case LT_U16: return measures_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, s);
-        case LT_I32: return measures_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, s);
-        case LT_U32: return measures_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, s);
+        case LT_U16: return measures_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s);
+        case LT_I32: return measures_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s);
+        case LT_U32: return measures_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

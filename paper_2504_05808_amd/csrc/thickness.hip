@@ -224,10 +224,9 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
 
 // ------------------------------------------------------------------ 3D z-fronts
 
-constexpr int FR_CHUNK = 64;        // slices per thread
 constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
 
-// One thread per (column, chunk of FR_CHUNK slices).  The kept centres of the
+// One thread per (column, chunk of `chunk` slices).  The kept centres of the
 // column within the chunk grown by the global reach R are gathered (batched loads)
 // into the thread's LDS list in z order; then for each slice of the chunk the
 // Pareto front over (value D, residual D - dz^2 > 0) of the centres within reach is
@@ -235,15 +234,15 @@ constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
 // list that would exceed FR_CAP marks the chunk's fronts as "rescan" (count 7);
 // the paint pass then takes every centre of the column instead (same result).
 __global__ void __launch_bounds__(256)
-fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, const uint32_t* __restrict__ gmax,
-         uint32_t* __restrict__ zf) {
+fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
+         const uint32_t* __restrict__ gmax, uint32_t* __restrict__ zf) {
     __shared__ uint32_t s_list[256 * FR_CAP];
     const int tid = threadIdx.y * 64 + threadIdx.x;
     uint32_t* list = s_list + tid;                 // stride 256: lane-interleaved, no bank conflicts
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
-    const int c0 = blockIdx.z * FR_CHUNK, c1 = min(nz, c0 + FR_CHUNK);
+    const int c0 = blockIdx.z * chunk, c1 = min(nz, c0 + chunk);
     const int R = open_reach(max((int)*gmax, 1));
     const int zlo = max(0, c0 - R), zhi = min(nz, c1 + R);
     const size_t plane = (size_t)ny * nx;
@@ -664,16 +663,16 @@ int paint_tile_rows(lt_ctx* ctx) {
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PAINT_DYN64);
     });
     // dynamic table + static reach table and work-item word
-    return ctx->lds_per_block >= dyn64 + REACH_TAB + 64 ? 64 : 32;
+    const bool fits64 = ctx->lds_per_block >= dyn64 + REACH_TAB + 64;
+    if (ctx->tune.paint_tile_rows == 32) return 32;
+    return fits64 ? 64 : 32;
 }
 
 template <typename L>
 static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* D,
-                                 uint32_t max_label, int32_t* lt, hipStream_t s) {
+                                 uint32_t max_label, int32_t* lt, void* scratch, hipStream_t s) {
     const ThickLayout lay = thick_layout(g, max_label);
-    lt_status st = ensure_scratch(ctx, lay.total);
-    if (st) return st;
-    char* base = (char*)ctx->scratch.ptr;
+    char* base = (char*)scratch;
     int32_t* bb = (int32_t*)(base + lay.bb);
     int32_t* maxd = (int32_t*)(base + lay.maxd);
     uint32_t* toff = (uint32_t*)(base + lay.toff);
@@ -709,8 +708,9 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         }
         {
             ProfScope _p(ctx, s, "fronts3d");
-            fronts3d<<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + FR_CHUNK - 1) / FR_CHUNK), b2, 0, s>>>(
-                kd, g.nx, g.ny, g.nz, gmax, zf);
+            const int chunk = ctx->tune.front_chunk > 0 ? ctx->tune.front_chunk : 64;
+            fronts3d<<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + chunk - 1) / chunk), b2, 0, s>>>(
+                kd, g.nx, g.ny, g.nz, chunk, gmax, zf);
         }
     } else {
         ProfScope _p(ctx, s, "pixels2d");
@@ -723,7 +723,10 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         plan_tiles<<<1, 1024, 0, s>>>(bb, nlab, tile_y, toff, counter);
     }
     const size_t lds = (size_t)TILE_LEVELS * tile_y * TILE_STRIDE * sizeof(uint32_t);
-    const int blocks = ctx->n_cu;
+    // two blocks per CU only when two 32-row tables fit in the LDS
+    const size_t per_block = lds + REACH_TAB + 64;
+    const int per_cu = (ctx->tune.paint_blocks_per_cu >= 2 && 2 * per_block <= ctx->lds_per_block) ? 2 : 1;
+    const int blocks = ctx->n_cu * per_cu;
     {
         ProfScope _p(ctx, s, "paint_tiles");
         if (g.ndim == 3)
@@ -738,11 +741,11 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
 
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           hipStream_t s) {
+                           void* scratch, hipStream_t s) {
     switch (dt) {
-        case LT_U16: return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, s);
-        case LT_I32: return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, s);
-        case LT_U32: return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, s);
+        case LT_U16: return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s);
+        case LT_I32: return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s);
+        case LT_U32: return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

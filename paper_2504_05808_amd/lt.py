@@ -39,6 +39,17 @@ class _Measures(ctypes.Structure):
         "roundness", "hist32")]
 
 
+class _Volume(ctypes.Structure):
+    _fields_ = [("labels", ctypes.c_void_p), ("ndim", ctypes.c_int), ("shape", ctypes.c_int64 * 3),
+                ("max_label", ctypes.c_uint32), ("dist_sq", ctypes.c_void_p), ("lt_sq", ctypes.c_void_p),
+                ("measures", _Measures)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("paint_tile_rows", ctypes.c_int), ("paint_blocks_per_cu", ctypes.c_int),
+                ("front_chunk", ctypes.c_int), ("batch_lanes", ctypes.c_int)]
+
+
 def load():
     """Load the built HIP library (fails loudly if it was not built)."""
     global _lib
@@ -59,6 +70,14 @@ def load():
     lib.lt_sync_status.argtypes = [P, V]
     lib.lt_ctx_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I)]
     lib.lt_profile_enable.argtypes = [P, I]
+    lib.lt_batch_create.argtypes = [P, ctypes.POINTER(_Volume), I, I, ctypes.POINTER(P)]
+    lib.lt_batch_run.argtypes = [P, V]
+    lib.lt_batch_destroy.argtypes = [P]
+    lib.lt_get_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+    lib.lt_set_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+    lib.lt_autotune.argtypes = [P, P, I, I, i64p, U32, ctypes.c_char_p, I, ctypes.POINTER(_Tuning)]
+    lib.lt_autotune_batch.argtypes = [P, ctypes.POINTER(_Volume), I, I, ctypes.c_char_p, I,
+                                      ctypes.POINTER(_Tuning)]
     lib.lt_profile_read.argtypes = [P, ctypes.POINTER(_KernelTime), I, ctypes.POINTER(I)]
     lib.lt_profile_reset.argtypes = [P]
     lib.lt_status_str.argtypes = [I]
@@ -67,7 +86,9 @@ def load():
     lib.lt_version.restype = ctypes.c_char_p
     for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
-              "lt_profile_reset", "lt_ctx_info"):
+              "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
+              "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
+              "lt_autotune_batch"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -136,6 +157,26 @@ class Context:
         lds = ctypes.c_uint64(0)
         _check(self._lib.lt_ctx_info(self._h, ctypes.byref(cu), ctypes.byref(lds), ctypes.byref(tr)))
         return {"n_cu": cu.value, "lds_per_block": lds.value, "paint_tile_rows": tr.value}
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check(self._lib.lt_get_tuning(self._h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _Tuning(**cur)
+        _check(self._lib.lt_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, labels: torch.Tensor, max_label: int, cache_path: str | None = None,
+                 repeats: int = 3) -> dict:
+        lab, dt = _labels(labels)
+        t = _Tuning()
+        _check(self._lib.lt_autotune(self._h, _ptr(lab), dt, lab.dim(), _shape(lab), int(max_label),
+                                     cache_path.encode() if cache_path else None, repeats,
+                                     ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in _Tuning._fields_}
 
     def profile(self, on: bool = True):
         _check(self._lib.lt_profile_enable(self._h, 1 if on else 0))
@@ -248,3 +289,63 @@ def measure(labels: torch.Tensor, max_label: int, hist: bool = False, ctx: Conte
 
 def version() -> str:
     return load().lt_version().decode()
+
+
+def _measures_struct(m: Measures) -> _Measures:
+    return _Measures(*[_ptr(getattr(m, k)).value for k in (
+        "volume", "shell_count", "max_lt_sq", "mean_lt", "shell_mean_lt", "sphericity", "roundness",
+        "hist32")])
+
+
+class Batch:
+    """Many volumes (one label dtype) captured into one graph; see lt_batch_create.
+
+    ``volumes`` is a list of (labels, max_label).  Outputs are allocated here and
+    exposed as ``outputs[i] = (dist_sq, lt_sq, Measures)``; they keep their
+    addresses for the life of the batch, so every run() rewrites them in place."""
+
+    def __init__(self, volumes, ctx: Context | None = None, autotune_cache: str | None = None,
+                 autotune_repeats: int = 0):
+        self.ctx = ctx or default_context()
+        self._lib = load()
+        self.labels = []
+        self.outputs = []
+        arr = (_Volume * len(volumes))()
+        dts = set()
+        for k, (labels, max_label) in enumerate(volumes):
+            lab, dt = _labels(labels)
+            dts.add(dt)
+            d = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+            t = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+            m = alloc_measures(int(max_label) + 1, lab.device)
+            self.labels.append(lab)
+            self.outputs.append((d, t, m))
+            shape = list(lab.shape) + [0] * (3 - lab.dim())
+            arr[k] = _Volume(_ptr(lab).value, lab.dim(), (ctypes.c_int64 * 3)(*shape), int(max_label),
+                             _ptr(d).value, _ptr(t).value, _measures_struct(m))
+        if len(dts) > 1:
+            raise TypeError("all volumes of a batch must share one label dtype")
+        self.dtype = dts.pop() if dts else LT_U16
+        self._vols = arr
+        if autotune_repeats > 0:
+            tt = _Tuning()
+            _check(self._lib.lt_autotune_batch(self.ctx.handle, arr, len(volumes), self.dtype,
+                                               autotune_cache.encode() if autotune_cache else None,
+                                               autotune_repeats, ctypes.byref(tt)))
+        h = ctypes.c_void_p()
+        _check(self._lib.lt_batch_create(self.ctx.handle, arr, len(volumes), self.dtype, ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(self._lib.lt_batch_run(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

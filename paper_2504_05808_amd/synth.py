@@ -361,18 +361,19 @@ def cfg3(seed: int = 3, shape=CFG3_SHAPE, n_objects: int = 2000, dtype=np.uint16
     return vol, dict(name="cfg3", objects=objs, n_objects=len(objs))
 
 
-def cfg4_sizes(seed: int = 4, n_volumes: int = 64):
+def cfg4_sizes(seed: int = 4, n_volumes: int = 64, edges=(96, 384), counts=(10, 500)):
     """Per-volume (edge, object count) for the batched workload."""
     rng = rng_for(seed)
-    edges = rng.integers(96, 385, n_volumes)
-    counts = rng.integers(10, 501, n_volumes)
-    return [(int(e), int(k)) for e, k in zip(edges, counts)]
+    e = rng.integers(edges[0], edges[1] + 1, n_volumes)
+    k = rng.integers(counts[0], counts[1] + 1, n_volumes)
+    return [(int(a), int(b)) for a, b in zip(e, k)]
 
 
-def cfg4_volume(i: int, seed: int = 4, n_volumes: int = 64):
+def cfg4_volume(i: int, seed: int = 4, n_volumes: int = 64, edges=(96, 384), counts=(10, 500)):
     """Volume i of the batch: cube of edge U{96..384} holding K ~ U{10..500} objects,
-    half ellipsoids and half superellipsoids from the 512^3 distribution, uint16."""
-    edge, k = cfg4_sizes(seed, n_volumes)[i]
+    half ellipsoids and half superellipsoids from the 512^3 distribution, uint16.
+    Reduced batches (smaller edges / counts) use the same recipe."""
+    edge, k = cfg4_sizes(seed, n_volumes, edges, counts)[i]
     rng = rng_for(seed * 100003 + i)
     vol = np.zeros((edge, edge, edge), dtype=np.uint16)
     objs = _place_until(vol, rng, k, ("ellipsoid", "superellipsoid"))

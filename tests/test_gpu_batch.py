@@ -1,0 +1,157 @@
+"""Batched form on the GPU: one captured graph over many volumes of uneven size
+gives bit-identical results to the plain per-volume calls, on every replay; the
+tuning knobs and the number of lanes change speed only; the autotuner caches its
+choice.  One batch volume is also checked against the CPU oracle."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lt_oracle as O
+from paper_2504_05808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("volume", "shell_count", "max_lt_sq", "mean_lt", "shell_mean_lt", "sphericity", "roundness")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_05808_amd import lt
+    lt.load()
+    return torch, lt
+
+
+def _vols3d():
+    out = []
+    for i in range(6):
+        v, _ = synth.cfg4_volume(i, n_volumes=6, edges=(40, 100), counts=(4, 30))
+        out.append(v)
+    rng = synth.rng_for(9)
+    out.append(synth.random_labels(rng, (23, 61, 70), n_labels=7, blob=5, dtype=np.uint16))
+    out.append(np.zeros((5, 6, 7), dtype=np.uint16))               # empty volume
+    return out
+
+
+def _snap(torch, d, t, m):
+    r = {"dist_sq": d.cpu().numpy().copy(), "lt_sq": t.cpu().numpy().copy()}
+    for k in KEYS:
+        r[k] = getattr(m, k).cpu().numpy().copy()
+    return r
+
+
+def _plain(gpu, vols):
+    torch, lt = gpu
+    refs = []
+    for v in vols:
+        lab = torch.from_numpy(v).cuda()
+        d, t, m = lt.measure(lab, int(v.max()) + 2)
+        lt.default_context().sync_status()
+        refs.append(_snap(torch, d, t, m))
+    return refs
+
+
+def _same(a, b):
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def _make_batch(gpu, vols, **kw):
+    torch, lt = gpu
+    labs = [torch.from_numpy(v).cuda() for v in vols]
+    return lt.Batch([(l, int(v.max()) + 2) for l, v in zip(labs, vols)], **kw)
+
+
+def test_batch_equals_plain_and_replays(gpu):
+    torch, lt = gpu
+    vols = _vols3d()
+    print("batch of", [v.shape for v in vols], flush=True)
+    refs = _plain(gpu, vols)
+    b = _make_batch(gpu, vols)
+    other = torch.from_numpy(synth.cfg1()[0]).cuda()
+    for rep in range(3):
+        for d, t, m in b.outputs:                  # poison outputs between replays
+            d.fill_(-7)
+            t.fill_(-7)
+            m.sphericity.fill_(-1.0)
+        b.run()
+        lt.default_context().sync_status()
+        for ref, out in zip(refs, b.outputs):
+            _same(ref, _snap(torch, *out))
+        lt.measure(other, int(other.max()))        # eager work between replays
+        torch.cuda.synchronize()
+    b.close()
+
+
+def test_batch_knobs_do_not_change_results(gpu):
+    torch, lt = gpu
+    vols = _vols3d()[:5]
+    refs = _plain(gpu, vols)
+    ctx = lt.default_context()
+    saved = ctx.get_tuning()
+    try:
+        for knobs in [dict(batch_lanes=1), dict(batch_lanes=3, paint_tile_rows=32, paint_blocks_per_cu=2),
+                      dict(batch_lanes=8, front_chunk=32), dict(front_chunk=128, paint_tile_rows=64)]:
+            ctx.set_tuning(**knobs)
+            print("knobs", ctx.get_tuning(), flush=True)
+            b = _make_batch(gpu, vols)
+            b.run()
+            ctx.sync_status()
+            for ref, out in zip(refs, b.outputs):
+                _same(ref, _snap(torch, *out))
+            b.close()
+            # the plain path under the same knobs
+            for ref, v in zip(refs, vols):
+                lab = torch.from_numpy(v).cuda()
+                d, t, m = lt.measure(lab, int(v.max()) + 2)
+                ctx.sync_status()
+                _same(ref, _snap(torch, d, t, m))
+    finally:
+        ctx.set_tuning(**saved)
+
+
+def test_batch_2d_int32_and_oracle(gpu):
+    torch, lt = gpu
+    base, _ = synth.cfg1()
+    vols = [base[:200, :230].copy(), base[40:, 10:].copy(), base[:64, :64].copy()]
+    refs = _plain(gpu, vols)
+    b = _make_batch(gpu, vols)
+    b.run()
+    lt.default_context().sync_status()
+    for ref, out in zip(refs, b.outputs):
+        _same(ref, _snap(torch, *out))
+    ora = O.measure(vols[2], max_label=int(vols[2].max()) + 2, per_object=False)
+    np.testing.assert_array_equal(b.outputs[2][1].cpu().numpy(), ora["lt_sq"])
+    b.close()
+
+
+def test_autotune_and_cache(gpu, tmp_path):
+    torch, lt = gpu
+    v, _ = synth.cfg4_volume(0, n_volumes=6, edges=(40, 100), counts=(4, 30))
+    lab = torch.from_numpy(v).cuda()
+    ctx = lt.default_context()
+    saved = ctx.get_tuning()
+    cache = str(tmp_path / "tune.json")
+    try:
+        best = ctx.autotune(lab, int(v.max()), cache_path=cache, repeats=2)
+        assert best["paint_tile_rows"] in (32, 64) and best["front_chunk"] in (32, 64, 128)
+        data = json.load(open(cache))
+        assert len(data) == 1 and "pipeline" in next(iter(data))
+        ctx.set_tuning(front_chunk=32 if best["front_chunk"] != 32 else 64)
+        again = ctx.autotune(lab, int(v.max()), cache_path=cache, repeats=2)
+        assert again["front_chunk"] == best["front_chunk"]
+        vols = _vols3d()[:4]
+        b = _make_batch(gpu, vols, autotune_cache=cache, autotune_repeats=2)
+        assert len(json.load(open(cache))) == 2
+        b.run()
+        ctx.sync_status()
+        for ref, out in zip(_plain(gpu, vols), b.outputs):
+            _same(ref, _snap(torch, *out))
+        b.close()
+    finally:
+        ctx.set_tuning(**saved)
