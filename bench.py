@@ -22,9 +22,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "voxels/s + objects/s for EDT+local thickness+measures at 512³; % HBM peak"
 
-# Algorithmic bytes per voxel of each kernel for uint16 labels (reads + writes that
-# the step must make at least once; neighbour re-reads served by caches excluded).
-# f = fraction of object voxels.
+# Peak of plain 32-bit vector ALU work: 256 CUs x 4 SIMDs x 16 lanes per clock
+# (one wave64 VALU instruction per CU per clock) at 2.4 GHz.
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+# Algorithmic bytes per launch of the streaming kernels for uint16 labels: each
+# kernel's inputs read once and outputs written once (neighbour re-reads served by
+# caches excluded).  n = voxels, f = fraction of object voxels.
 def kernel_bytes(name: str, n: int, f: float, label_bytes: int = 2) -> float | None:
     lb = label_bytes
     table = {
@@ -32,11 +37,76 @@ def kernel_bytes(name: str, n: int, f: float, label_bytes: int = 2) -> float | N
         "edt_pass_y": (2 + lb + 4) * n,             # g, labels -> d2
         "edt_pass_z": (4 + lb + 4) * n,             # d2, labels -> D
         "bbox_runs": lb * n,                        # labels
-        "columns3d": 4 * n + 4 * (1 - f) * n + 4 * f * n,   # D; LT=0 on background; front plane 0
-        "paint_tiles": (lb + 4 + 4) * f * n,        # labels + front of object voxels; LT out
+        "prune3d": (lb + 4) * n + 4 * f * n,        # labels, D -> kept-centre field of object voxels
+        "fronts3d": 4 * f * n + 16 * f * n + 4 * (1 - f) * n,   # kept field -> 4 front planes; LT = 0 outside
+        "paint_tiles": (lb + 16 + 4) * f * n,       # labels + fronts of object voxels -> LT
         "object_sums": (lb + 4) * n,                # labels + LT
     }
     return table.get(name)
+
+
+def lattice_tables(dmax: int):
+    """N[d] = #{q in Z^3 : |q|^2 < d} and, for the neighbour offsets o with |o|^2 =
+    1, 2, 3, T_c[d] = max{|q - o|^2 : |q|^2 < d} (-1 for d = 0), d = 0..dmax."""
+    R = int(np.ceil(np.sqrt(dmax))) + 1
+    r = np.arange(-R, R + 1)
+    qz, qy, qx = np.meshgrid(r, r, r, indexing="ij")
+    q2 = (qx * qx + qy * qy + qz * qz).ravel()
+    order = np.argsort(q2, kind="stable")
+    q2s = q2[order]
+    d = np.arange(dmax + 1)
+    N = np.searchsorted(q2s, d, side="left")             # points with |q|^2 < d
+    T = []
+    for o in ((1, 0, 0), (1, 1, 0), (1, 1, 1)):
+        e = ((qx - o[0]) ** 2 + (qy - o[1]) ** 2 + (qz - o[2]) ** 2).ravel()[order]
+        pm = np.maximum.accumulate(e)
+        T.append(np.where(N > 0, pm[np.maximum(N - 1, 0)], -1))
+    return N.astype(np.int64), np.stack(T).astype(np.int64)
+
+
+def ball_cover_work(lab, D) -> tuple[int, int]:
+    """Ball-cover algorithmic work of the 3D local thickness: the sum over kept
+    centres x of |B(x)| = #{q : |q - x|^2 < D(x)}; a centre is dropped when its open
+    ball lies inside the open ball of a 26-neighbour of the same label
+    (T_|o|^2[D(x)] < D(y)).  Computed with torch tensor ops on the resident fields
+    (outside any timed region).  Returns (work, kept centres)."""
+    import torch
+    dmax = int(D.max())
+    N, T = lattice_tables(dmax)
+    Nt = torch.from_numpy(N).to(D.device)
+    Tt = torch.from_numpy(T).to(D.device)
+    Dl = D.long()
+    L = lab.int()
+    obj = L != 0
+    covered = torch.zeros_like(obj)
+    Z, Y, X = D.shape
+    Tc = [Tt[c][Dl] for c in range(3)]
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                c = abs(dz) + abs(dy) + abs(dx)
+                if c == 0:
+                    continue
+                def sl(a, o, n):
+                    return slice(max(0, -o), n - max(0, o)), slice(max(0, o), n - max(0, -o))
+                (sz, tz), (sy, ty), (sx, tx) = sl(0, dz, Z), sl(0, dy, Y), sl(0, dx, X)
+                same = L[sz, sy, sx] == L[tz, ty, tx]
+                inside = Tc[c - 1][sz, sy, sx] < Dl[tz, ty, tx]
+                covered[sz, sy, sx] |= same & inside
+    kept = obj & ~covered
+    work = int(Nt[Dl][kept].sum())
+    return work, int(kept.sum())
+
+
+def copy_calibration(dev, nbytes: int = 1 << 30):
+    """One plain device copy of a known size, so that the HBM counters of a profiled
+    run can be scaled: bytes / FETCH_SIZE and bytes / WRITE_SIZE of this copy."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: {nbytes} bytes read and written", flush=True)
 
 
 def cpu_baseline(vol: np.ndarray, seconds: float, threads: int) -> dict:
@@ -147,6 +217,75 @@ def batch_bench(args):
     b.close()
 
 
+MLP_FWD_FLOPS = 2 * (34 * 64 + 64 * 64 + 64 * 64 + 64)     # per object, unpadded layer sizes
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_bench(args):
+    """Learned correction on its own: AdamW training steps (batch 256) and corrected
+    sphericity for 20000 objects (the evaluation volume's object count), synthetic
+    features; one line with both rates."""
+    import torch
+
+    from paper_2504_05808_amd import lt
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = lt.default_context()
+    g = torch.Generator().manual_seed(0)
+    n_obj, B = 20000, 256
+    x = torch.rand((n_obj, 34), generator=g).to(dev)
+    y = torch.randn(n_obj, generator=g).to(dev)
+    s_lt = (0.7 + 0.3 * torch.rand(n_obj, generator=g)).to(dev)
+    net = lt.MLP(seed=0, ctx=ctx)
+    batches = [(x[i:i + B].contiguous(), y[i:i + B].contiguous()) for i in range(0, n_obj - B + 1, B)]
+
+    def timed(fn, k):
+        for i in range(args.warmup):
+            fn(i)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for i in range(k):
+            fn(i)
+        z.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(z) / k
+
+    ctx.profile(True)
+    ctx.profile_reset()
+    n_train = max(args.steps, 50)
+    ms_train = timed(lambda i: net.train_step(*batches[i % len(batches)], lr=1e-3, weight_decay=1e-4), n_train)
+    ms_corr = timed(lambda i: net.correct(x, s_lt), args.steps)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.sync_status()
+    gem = prof.get("mfma_gemm")
+    train_flops = 3 * MLP_FWD_FLOPS * B
+    infer_flops = MLP_FWD_FLOPS * n_obj
+    total_flops = (n_train + args.warmup) * train_flops + (args.steps + args.warmup) * infer_flops
+    roof = None
+    if gem:
+        ach = total_flops / (gem[0] * 1e-3) / 1e12           # all product FLOPs / all GEMM time
+        roof = {"bound": "mfma", "kernel": "mfma_gemm", "achieved": round(ach, 4), "peak": BF16_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 6), "traffic": None,
+                "avg_ms": round(gem[0] / gem[1], 5), "launches": gem[1],
+                "note": "algorithmic products (unpadded 34-64-64-64-1, backward = 2x forward) over "
+                        "the summed GEMM kernel time; launch- and latency-bound at these sizes"}
+    print(json.dumps({
+        "metric": "learned correction: corrected sphericities per second and training samples per second",
+        "value": n_obj / (ms_corr * 1e-3), "unit": "objects/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_corr, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "34-64-64-64-1 SiLU MLP, 20000 objects per correction call, "
+                               "AdamW batch 256"},
+        "train": {"ms_per_step": ms_train, "samples_per_s": B / (ms_train * 1e-3)},
+        "roofline": roof,
+    }), flush=True)
+    net.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +296,9 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="measure the batched graph form against per-volume launches instead")
     ap.add_argument("--batch-volumes", type=int, default=64)
+    ap.add_argument("--mlp", action="store_true", help="measure the learned correction instead")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (reference for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
@@ -164,6 +306,9 @@ def main():
         sys.exit(2)
     if args.batch:
         batch_bench(args)
+        return
+    if args.mlp:
+        mlp_bench(args)
         return
 
     import torch
@@ -188,6 +333,8 @@ def main():
     m = lt.alloc_measures(max_label + 1, dev)
 
     print(f"# device {ctx.info()}", flush=True)
+    if args.copy_calibration:
+        copy_calibration(dev)
 
     def step():
         lt.edt(lab, out=d, ctx=ctx)
@@ -218,13 +365,28 @@ def main():
     kernels = {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in prof.items()}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     dom_ms = kernels[dom]["avg_ms"]
-    dom_bytes = kernel_bytes(dom, N, f_obj)
+    for k, v in kernels.items():
+        b = kernel_bytes(k, N, f_obj)
+        if b is not None:
+            v["GBs"] = b / (v["avg_ms"] * 1e-3) / 1e9
     roof = None
-    if dom_bytes is not None:
-        ach = dom_bytes / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": dom_bytes, "avg_ms": round(dom_ms, 4)}
+    work = kept = None
+    if dom == "paint_tiles":
+        work, kept = ball_cover_work(lab, d)
+        ops = 2.0 * work                             # a compare and a max per covered point
+        ach = ops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "Tops/s", "frac": round(ach / ALU_PEAK_TOPS, 4), "traffic": None,
+                "work_per_launch": ops, "avg_ms": round(dom_ms, 4),
+                "note": "ball-cover work: 2 x sum over kept centres of |B(x)| (compare + max per "
+                        "covered lattice point) / kernel time; peak = 32-bit VALU lanes x clock"}
+    else:
+        b = kernel_bytes(dom, N, f_obj)
+        if b is not None:
+            ach = b / (dom_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": b, "avg_ms": round(dom_ms, 4)}
     stage = {"edt": 0.0, "thickness": 0.0, "measures": 0.0}
     for k, v in kernels.items():
         tot = v["avg_ms"] * v["launches"] / args.steps
@@ -266,6 +428,9 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "device": ctx.info(),
         "kernel_ms": {k: round(v["avg_ms"], 4) for k, v in kernels.items()},
+        "kernel_GBs": {k: round(v["GBs"], 1) for k, v in kernels.items() if "GBs" in v},
+        "ball_cover": None if work is None else {"work_points": work, "kept_centres": kept,
+                                                 "points_per_object_voxel": work / (f_obj * N)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

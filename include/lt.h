@@ -191,6 +191,65 @@ lt_status lt_autotune(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
 lt_status lt_autotune_batch(lt_ctx* ctx, const lt_volume* vols, int n_volumes, lt_dtype dtype,
                             const char* cache_path, int repeats, lt_tuning* best);
 
+/* ---------------------------------------------------------------- learned correction
+ * A 34 -> 64 -> 64 -> 64 -> 1 SiLU network that corrects the spheroid sphericity
+ * toward a mesh-based sphericity.  Features per object (lt_mlp_features): the
+ * 32-bin local-thickness histogram of lt_measures.hist32, log V and
+ * mean_lt / V^(1/3).  The network sees the features standardised with
+ * (mean, stdev) and predicts (delta - target_shift) / target_scale, delta being the
+ * correction to add to the closed form.  Products run as BF16 MFMA with FP32
+ * accumulation; master weights and AdamW moments are FP32.  All arrays are device
+ * arrays unless noted; calls are stream-ordered. */
+typedef struct lt_mlp lt_mlp;
+/* He-uniform weights from `seed`, zero biases; identity normalisation, open guard. */
+lt_status lt_mlp_create(lt_ctx* ctx, uint64_t seed, lt_mlp** out);
+lt_status lt_mlp_destroy(lt_mlp* mlp);
+/* Host arrays of 34 feature means and spreads; target = (delta - shift) / scale. */
+lt_status lt_mlp_set_normalization(lt_mlp* mlp, const float* mean, const float* stdev,
+                                   float target_shift, float target_scale);
+/* Host arrays of 34 per-feature bounds and the largest |delta| the correction may
+ * apply (the training set's ranges). */
+lt_status lt_mlp_set_guard(lt_mlp* mlp, const float* fmin, const float* fmax, float max_abs_delta);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8, decoupled weight decay on matrices) on
+ * the mean squared error of the standardised target y (B values) for features x
+ * (B x 34); B a positive multiple of 16.  lr = 0 computes gradients only.  If
+ * loss_out is not NULL it receives the sum of squared errors (one float). */
+lt_status lt_mlp_train_step(lt_mlp* mlp, const float* x, const float* y, int batch, float lr,
+                            float weight_decay, float* loss_out, void* stream);
+/* delta (B floats) = de-standardised network output for features x (B x 34). */
+lt_status lt_mlp_infer(lt_mlp* mlp, const float* x, int batch, float* delta, void* stream);
+/* Features x (n x 34) from lt_object_measures outputs (hist32 [n x 32], volume,
+ * mean_lt); absent objects give non-finite features. */
+lt_status lt_mlp_features(lt_ctx* ctx, const float* hist32, const uint64_t* volume,
+                          const float* mean_lt, uint32_t n, float* x, void* stream);
+/* s_corr = s_lt + delta where the guard accepts the prediction (every feature within
+ * its bounds, delta finite and |delta| <= max_abs_delta), else s_lt; *n_fallback
+ * (device, not cleared here) is incremented once per rejected object.
+ * delta_scratch holds n floats. */
+lt_status lt_mlp_correct(lt_mlp* mlp, const float* x, const float* s_lt, int n,
+                         float* delta_scratch, float* s_corr, uint32_t* n_fallback, void* stream);
+/* Whole model state (weights, moments, step, normalisation, guard) as a host blob
+ * of lt_mlp_state_size() bytes, for checkpoint and resume. */
+size_t lt_mlp_state_size(void);
+lt_status lt_mlp_get_state(lt_mlp* mlp, void* blob, size_t bytes);
+lt_status lt_mlp_set_state(lt_mlp* mlp, const void* blob, size_t bytes);
+/* Device pointers to the FP32 master weights and the last step's gradients (packed
+ * layout: W1[64][48] b1[64] W2[64][64] b2 W3[64][64] b3 W4[16][64] b4[16], unused
+ * pads zero) and the packed length. */
+lt_status lt_mlp_buffers(lt_mlp* mlp, float** weights, float** grads, int* n_param);
+/* Host copy (after a device synchronisation) of one packed array: which = 0 master
+ * weights, 1 last gradients, 2 first moments, 3 second moments; `host` holds at
+ * least n_param floats (n), else LT_E_WORKSPACE. */
+lt_status lt_mlp_read(lt_mlp* mlp, int which, float* host, size_t n);
+
+/* The network's matrix-product kernel on its own: C (M x N, FP32, row stride ldc) =
+ * A (M x K) * B (K x N) for BF16 inputs (uint16 bit patterns), with A(i, k) at
+ * A[i * lda + k] (or A[k * lda + i] when trans_a) and B(k, j) at B[k * ldb + j] (or
+ * B[j * ldb + k] when trans_b); M, N, K multiples of 16.  Products use
+ * v_mfma_f32_16x16x16_bf16 with FP32 accumulation. */
+lt_status lt_bf16_gemm(int M, int N, int K, const uint16_t* A, int lda, int trans_a,
+                       const uint16_t* B, int ldb, int trans_b, float* C, int ldc, void* stream);
+
 /* Kernel timing (tracing).  When enabled, every kernel the library launches is
  * bracketed by two HIP events recorded on the launch stream; lt_profile_read waits
  * for the pending events and returns per-kernel totals accumulated since the last

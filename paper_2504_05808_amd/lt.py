@@ -349,3 +349,159 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned correction
+
+N_FEATURES = 34
+
+
+def _mlp_lib():
+    lib = load()
+    if not getattr(lib, "_mlp_bound", False):
+        P, I, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p
+        f = ctypes.c_float
+        lib.lt_mlp_create.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(P)]
+        lib.lt_mlp_destroy.argtypes = [P]
+        lib.lt_mlp_set_normalization.argtypes = [P, P, P, f, f]
+        lib.lt_mlp_set_guard.argtypes = [P, P, P, f]
+        lib.lt_mlp_train_step.argtypes = [P, P, P, I, f, f, P, V]
+        lib.lt_mlp_infer.argtypes = [P, P, I, P, V]
+        lib.lt_mlp_features.argtypes = [P, P, P, P, ctypes.c_uint32, P, V]
+        lib.lt_mlp_correct.argtypes = [P, P, P, I, P, P, P, V]
+        lib.lt_mlp_state_size.restype = ctypes.c_size_t
+        lib.lt_mlp_get_state.argtypes = [P, P, ctypes.c_size_t]
+        lib.lt_mlp_set_state.argtypes = [P, P, ctypes.c_size_t]
+        lib.lt_mlp_buffers.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I)]
+        lib.lt_bf16_gemm.argtypes = [I, I, I, P, I, I, P, I, I, P, I, V]
+        lib.lt_mlp_read.argtypes = [P, I, P, ctypes.c_size_t]
+        for name in ("lt_mlp_create", "lt_mlp_destroy", "lt_mlp_set_normalization", "lt_mlp_set_guard",
+                     "lt_mlp_train_step", "lt_mlp_infer", "lt_mlp_features", "lt_mlp_correct",
+                     "lt_mlp_get_state", "lt_mlp_set_state", "lt_mlp_buffers", "lt_bf16_gemm", "lt_mlp_read"):
+            getattr(lib, name).restype = I
+        lib._mlp_bound = True
+    return lib
+
+
+def _host_f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bf16_gemm(A: torch.Tensor, B: torch.Tensor, trans_a: bool = False, trans_b: bool = False,
+              stream=None) -> torch.Tensor:
+    """C = op(A) op(B) for bfloat16 device matrices with the library's MFMA kernel."""
+    lib = _mlp_lib()
+    assert A.dtype == torch.bfloat16 and B.dtype == torch.bfloat16
+    A, B = A.contiguous(), B.contiguous()
+    M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
+    K2, N = (B.shape[1], B.shape[0]) if trans_b else B.shape
+    assert K == K2
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib.lt_bf16_gemm(M, N, K, _ptr(A), A.shape[1], int(trans_a), _ptr(B), B.shape[1], int(trans_b),
+                            _ptr(C), N, _stream(stream)))
+    return C
+
+
+class MLP:
+    """Sphericity-correction network (see the lt_mlp_* declarations in lt.h)."""
+
+    def __init__(self, seed: int = 0, ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        self._lib = _mlp_lib()
+        h = ctypes.c_void_p()
+        _check(self._lib.lt_mlp_create(self.ctx.handle, int(seed), ctypes.byref(h)))
+        self._h = h
+        self._loss = torch.zeros(1, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.lt_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_normalization(self, mean, std, target_shift: float, target_scale: float):
+        m, mp = _host_f32(mean)
+        s, sp = _host_f32(std)
+        _check(self._lib.lt_mlp_set_normalization(self._h, mp, sp, float(target_shift), float(target_scale)))
+
+    def set_guard(self, fmin, fmax, max_abs_delta: float):
+        a, ap = _host_f32(fmin)
+        b, bp = _host_f32(fmax)
+        _check(self._lib.lt_mlp_set_guard(self._h, ap, bp, float(max_abs_delta)))
+
+    def train_step(self, x: torch.Tensor, y: torch.Tensor, lr: float, weight_decay: float = 0.0,
+                   stream=None) -> torch.Tensor:
+        """One AdamW step; returns the (device) sum of squared errors."""
+        x, y = x.contiguous(), y.contiguous()
+        _check(self._lib.lt_mlp_train_step(self._h, _ptr(x), _ptr(y), x.shape[0], float(lr),
+                                           float(weight_decay), _ptr(self._loss), _stream(stream)))
+        return self._loss
+
+    def infer(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        x = x.contiguous()
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(self._lib.lt_mlp_infer(self._h, _ptr(x), x.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def correct(self, x: torch.Tensor, s_lt: torch.Tensor, stream=None):
+        """(s_corr, n_fallback) with the guard applied."""
+        x, s_lt = x.contiguous(), s_lt.contiguous()
+        n = x.shape[0]
+        delta = torch.empty(n, dtype=torch.float32, device=x.device)
+        out = torch.empty(n, dtype=torch.float32, device=x.device)
+        nf = torch.zeros(1, dtype=torch.int32, device=x.device)
+        _check(self._lib.lt_mlp_correct(self._h, _ptr(x), _ptr(s_lt), n, _ptr(delta), _ptr(out), _ptr(nf),
+                                        _stream(stream)))
+        return out, nf
+
+    def buffers(self):
+        w, g, n = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int(0)
+        _check(self._lib.lt_mlp_buffers(self._h, ctypes.byref(w), ctypes.byref(g), ctypes.byref(n)))
+        return w.value, g.value, n.value
+
+    def _read(self, which: int):
+        import numpy as np
+        _, _, n = self.buffers()
+        out = np.empty(n, dtype=np.float32)
+        _check(self._lib.lt_mlp_read(self._h, which, out.ctypes.data_as(ctypes.c_void_p), n))
+        return out
+
+    def params(self):
+        """FP32 master weights (packed layout), host copy."""
+        return self._read(0)
+
+    def grads(self):
+        """Gradients of the last step (packed layout), host copy."""
+        return self._read(1)
+
+    def moments(self):
+        """AdamW first and second moments, host copies."""
+        return self._read(2), self._read(3)
+
+    def get_state(self) -> bytes:
+        size = self._lib.lt_mlp_state_size()
+        buf = ctypes.create_string_buffer(size)
+        _check(self._lib.lt_mlp_get_state(self._h, buf, size))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(self._lib.lt_mlp_set_state(self._h, buf, len(blob)))
+
+
+def mlp_features(m: Measures, ctx: Context | None = None, stream=None) -> torch.Tensor:
+    """Per-object network features (max_label + 1 rows x 34) from measures with hist32."""
+    assert m.hist32 is not None, "object_measures(..., hist=True) is needed for the features"
+    ctx = ctx or default_context()
+    n = m.volume.numel()
+    x = torch.empty((n, N_FEATURES), dtype=torch.float32, device=m.volume.device)
+    _check(_mlp_lib().lt_mlp_features(ctx.handle, _ptr(m.hist32), _ptr(m.volume), _ptr(m.mean_lt), n,
+                                      _ptr(x), _stream(stream)))
+    return x

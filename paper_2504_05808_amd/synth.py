@@ -380,6 +380,50 @@ def cfg4_volume(i: int, seed: int = 4, n_volumes: int = 64, edges=(96, 384), cou
     return vol, dict(name=f"cfg4[{i}]", objects=objs, n_objects=len(objs))
 
 
+def _cfg5_octant(args):
+    seed, k, n_objects, edge = args
+    rng = rng_for(seed * 100003 + k)
+    vol = np.zeros((edge, edge, edge), dtype=np.uint16)
+    objs = _place_until(vol, rng, n_objects, ("superellipsoid",))
+    return vol, len(objs)
+
+
+def cfg5_volume(seed: int = 6, edge: int = 1024, n_objects: int = 20000, workers: int | None = None,
+                use_cache: bool = True):
+    """Evaluation volume of the learned correction: edge^3 uint32 holding ~n_objects
+    objects of the 512^3 distribution.  The volume is built as 8 independent octants
+    (each placed like the 512^3 volume with n_objects / 8 objects, seeded per octant,
+    objects never crossing an octant face), generated in parallel processes; labels
+    are numbered octant by octant."""
+    key = f"cfg5_s{seed}_{edge}_{n_objects}_v1"
+    path = _cache_path(key + ".npz") if use_cache else None
+    if path and os.path.exists(path):
+        with np.load(path) as z:
+            return z["vol"], dict(name="cfg5", n_objects=int(z["n"]), cached=True)
+    h = edge // 2
+    jobs = [(seed, k, n_objects // 8, h) for k in range(8)]
+    workers = workers or min(8, os.cpu_count() or 1)
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            parts = pool.map(_cfg5_octant, jobs)
+    else:
+        parts = [_cfg5_octant(j) for j in jobs]
+    vol = np.zeros((edge, edge, edge), dtype=np.uint32)
+    base = 0
+    for k, (v, n) in enumerate(parts):
+        z0, y0, x0 = (k >> 2) * h, ((k >> 1) & 1) * h, (k & 1) * h
+        sub = v.astype(np.uint32)
+        sub[sub != 0] += base
+        vol[z0:z0 + h, y0:y0 + h, x0:x0 + h] = sub
+        base += n
+    if path:
+        tmp = path + f".tmp{os.getpid()}.npz"
+        np.savez(tmp, vol=vol, n=base)
+        os.replace(tmp, path)
+    return vol, dict(name="cfg5", n_objects=base)
+
+
 def random_labels(rng: np.random.Generator, shape, n_labels: int = 4, p_bg: float = 0.3,
                   blob: int = 2, dtype=np.int32):
     """Small random label arrays for brute-force checks: blocky label patches with

@@ -71,3 +71,20 @@ def test_binding_rejects_host_and_bad_dtype_tensors():
         lt._labels(torch.zeros((4, 4), dtype=torch.float32))
     with pytest.raises(ValueError):
         lt._labels(torch.zeros((4, 4), dtype=torch.int32))
+
+
+def test_learned_correction_argument_errors():
+    """The network and GEMM entry points check arguments before any device call."""
+    lib = lt._mlp_lib()
+    out = ctypes.c_void_p()
+    assert lib.lt_mlp_create(None, 0, ctypes.byref(out)) == 1
+    assert lib.lt_mlp_destroy(None) == 0
+    assert lib.lt_mlp_train_step(None, None, None, 16, 0.0, 0.0, None, None) == 1
+    assert lib.lt_mlp_infer(None, None, 4, None, None) == 1
+    assert lib.lt_mlp_read(None, 0, None, 0) == 1
+    assert lib.lt_mlp_features(None, None, None, None, 0, None, None) == 1
+    assert lib.lt_bf16_gemm(15, 16, 16, None, 16, 0, None, 16, 0, None, 16, None) == 3
+    assert lib.lt_bf16_gemm(16, 16, 8, None, 16, 0, None, 16, 0, None, 16, None) == 3
+    assert lib.lt_bf16_gemm(0, 16, 16, None, 16, 0, None, 16, 0, None, 16, None) == 0
+    assert lib.lt_bf16_gemm(16, 16, 16, None, 16, 0, None, 16, 0, None, 16, None) == 1
+    assert lib.lt_mlp_state_size() == (3 * 12496 + 4 * 34 + 3 + 2) * 4

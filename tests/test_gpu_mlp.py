@@ -1,0 +1,317 @@
+"""GPU checks of the learned sphericity correction through the C ABI.
+
+* the BF16 MFMA product against exact products of the same BF16 values (FP32
+  accumulation of exact BF16 x BF16 products: error <= K u_32 sum |a b|);
+* the network's forward pass and gradients against the FP64 oracle network with
+  BF16 rounding at the device's rounding points (remaining differences: FP32
+  accumulation and the rare BF16 rounding decision that an FP32 / FP64 difference
+  flips, bounded below);
+* AdamW's first step against its closed form (the bias-corrected moments of one
+  gradient give an update of lr * g / (|g| + eps));
+* determinism, state round trip, the guard, and the features computed from the
+  measures against the CPU oracle's;
+* training on the oracle-made data set (40000 isolated objects, every fifth held
+  out) improves the held-out error of the sphericity against the mesh target over
+  both the closed form and an affine recalibration of it.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lt_oracle as O
+from oracle import mlp_ref as R
+from paper_2504_05808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DATASET = os.path.join(ROOT, "tests", "golden", "mlp_set.npz")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_05808_amd import lt
+    lt.load()
+    return torch, lt
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _bf16_tensor(torch, a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16)
+
+
+# ------------------------------------------------------------------ GEMM
+
+
+@pytest.mark.parametrize("mnk", [(16, 16, 16), (32, 48, 64), (64, 16, 272), (48, 64, 16)])
+@pytest.mark.parametrize("ta", [False, True])
+@pytest.mark.parametrize("tb", [False, True])
+def test_bf16_gemm_matches_exact_products(gpu, mnk, ta, tb):
+    torch, lt = gpu
+    M, N, K = mnk
+    _note(f"gemm M={M} N={N} K={K} ta={ta} tb={tb}")
+    rng = np.random.default_rng(M * 1000 + N * 10 + K + 2 * ta + tb)
+    a = rng.standard_normal((M, K)) * np.exp(rng.uniform(-3, 3, (M, 1)))
+    b = rng.standard_normal((K, N))
+    A = _bf16_tensor(torch, a.T.copy() if ta else a)
+    B = _bf16_tensor(torch, b.T.copy() if tb else b)
+    C = lt.bf16_gemm(A.cuda(), B.cuda(), trans_a=ta, trans_b=tb).cpu().double().numpy()
+    a64 = A.double().numpy()
+    b64 = B.double().numpy()
+    a64 = a64.T if ta else a64
+    b64 = b64.T if tb else b64
+    ref = a64 @ b64
+    bound = K * 2.0 ** -24 * (np.abs(a64) @ np.abs(b64)) + 1e-30
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+# ------------------------------------------------------------------ network vs oracle
+
+
+def _norm(rng):
+    mean = rng.normal(0, 1, R.IN).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, R.IN).astype(np.float32)
+    return mean, std
+
+
+def _inputs(rng, B, mean, std):
+    return (mean + std * rng.standard_normal((B, R.IN))).astype(np.float32)
+
+
+def test_forward_matches_oracle(gpu):
+    """Rows agree with the BF16-rounded FP64 network to 1e-4 (99%) and 1e-2 (all):
+    a flipped BF16 decision moves one activation by one BF16 step."""
+    torch, lt = gpu
+    rng = np.random.default_rng(11)
+    net = lt.MLP(seed=7)
+    mean, std = _norm(rng)
+    shift, scale = 0.03, 0.2
+    net.set_normalization(mean, std, shift, scale)
+    p = net.params().astype(np.float64)
+    inv = 1.0 / std.astype(np.float64)
+    for B in (1, 16, 37, 300):
+        _note(f"forward B={B}")
+        x = _inputs(rng, B, mean, std)
+        got = net.infer(torch.from_numpy(x).cuda()).cpu().double().numpy()
+        pred, _ = R.forward(p, x, mean, inv, bf16_ops=True)
+        ref = pred * scale + shift
+        err = np.abs(got - ref) / scale
+        assert np.quantile(err, 0.99) <= 1e-4 and err.max() <= 1e-2, (B, err.max())
+
+
+def _block_errors(g, r):
+    gu, ru = R.unpack(g), R.unpack(r)
+    return {k: float(np.linalg.norm(gu[k] - ru[k]) / max(np.linalg.norm(ru[k]), 1e-30)) for k in gu}
+
+
+@pytest.mark.parametrize("B", [16, 64, 256])
+def test_gradients_match_oracle(gpu, B):
+    """lr = 0: gradients only.  Each parameter block within 2e-3 relative (norm) of
+    the oracle's; pads zero; the loss output is the sum of squared errors."""
+    torch, lt = gpu
+    _note(f"gradients B={B}")
+    rng = np.random.default_rng(100 + B)
+    net = lt.MLP(seed=3)
+    mean, std = _norm(rng)
+    net.set_normalization(mean, std, 0.0, 1.0)
+    p = net.params().astype(np.float64)
+    x = _inputs(rng, B, mean, std)
+    y = rng.normal(0, 1, B).astype(np.float32)
+    loss = net.train_step(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), lr=0.0)
+    sse = float(loss.cpu()[0])
+    g = net.grads().astype(np.float64)
+    inv = 1.0 / std.astype(np.float64)
+    ref = R.backward(p, x, y, mean, inv, bf16_ops=True)
+    errs = _block_errors(g, ref)
+    assert max(errs.values()) <= 2e-3, errs
+    gu = R.unpack(g)
+    assert np.all(gu["W1"][:, R.IN:] == 0) and np.all(gu["W4"][1:] == 0) and np.all(gu["b4"][1:] == 0)
+    pred, _ = R.forward(p, x, mean, inv, bf16_ops=True)
+    assert sse == pytest.approx(float(np.sum((pred - y) ** 2)), rel=1e-3)
+    np.testing.assert_array_equal(net.params(), p.astype(np.float32))       # lr = 0: unchanged
+
+
+def test_adamw_first_step_closed_form(gpu):
+    torch, lt = gpu
+    rng = np.random.default_rng(5)
+    net = lt.MLP(seed=9)
+    w0 = net.params().astype(np.float64)
+    x = rng.standard_normal((32, R.IN)).astype(np.float32)
+    y = rng.standard_normal(32).astype(np.float32)
+    lr, wd = 1e-3, 0.1
+    net.train_step(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), lr=lr, weight_decay=wd)
+    g = net.grads().astype(np.float64)
+    w1 = net.params().astype(np.float64)
+    is_bias = np.zeros(R.N_PARAM, bool)
+    for k in ("b1", "b2", "b3", "b4"):
+        o, n = R.OFF[k]
+        is_bias[o:o + n] = True
+    decay = np.where(is_bias, 0.0, lr * wd)
+    expect = w0 - decay * w0 - lr * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(w1, expect, rtol=0, atol=2e-7 + 1e-6 * np.abs(w0))
+    m, v = net.moments()
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=5e-5, atol=0)     # 1 - 0.999f = 0.001 (1 - 1.3e-5)
+
+
+def _train(torch, net, x, y, steps, lr, batch=64, seed=0):
+    rng = np.random.default_rng(seed)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    for _ in range(steps):
+        idx = torch.from_numpy(rng.choice(len(x), batch, replace=False)).cuda()
+        net.train_step(xd[idx], yd[idx], lr=lr, weight_decay=1e-4)
+
+
+def test_training_is_deterministic_and_state_round_trips(gpu):
+    torch, lt = gpu
+    rng = np.random.default_rng(21)
+    mean, std = _norm(rng)
+    x = _inputs(rng, 512, mean, std)
+    y = rng.normal(0, 1, 512).astype(np.float32)
+    a, b = lt.MLP(seed=1), lt.MLP(seed=1)
+    for n in (a, b):
+        n.set_normalization(mean, std, 0.1, 0.5)
+        _train(torch, n, x, y, 20, 3e-3)
+    np.testing.assert_array_equal(a.params(), b.params())
+    blob = a.get_state()
+    c = lt.MLP(seed=99)
+    c.set_state(blob)
+    assert c.get_state() == blob
+    xq = torch.from_numpy(x[:100]).cuda()
+    np.testing.assert_array_equal(a.infer(xq).cpu().numpy(), c.infer(xq).cpu().numpy())
+    for n in (a, c):                                 # resume: same next step
+        _train(torch, n, x, y, 3, 3e-3, seed=5)
+    np.testing.assert_array_equal(a.params(), c.params())
+    d = lt.MLP(seed=1)
+    assert not np.array_equal(d.params(), a.params())
+
+
+def test_training_reduces_loss(gpu):
+    torch, lt = gpu
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((1024, R.IN)).astype(np.float32)
+    y = (np.tanh(x[:, 0] * x[:, 1]) + 0.5 * x[:, 2] ** 2 - 0.5).astype(np.float32)
+    net = lt.MLP(seed=2)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    first = float(net.train_step(xd, yd, lr=0.0).cpu()[0]) / len(x)
+    _train(torch, net, x, y, 400, 3e-3, batch=128)
+    last = float(net.train_step(xd, yd, lr=0.0).cpu()[0]) / len(x)
+    assert last < 0.1 * first, (first, last)
+
+
+def test_guard(gpu):
+    torch, lt = gpu
+    rng = np.random.default_rng(3)
+    net = lt.MLP(seed=4)
+    x = rng.uniform(-1, 1, (40, R.IN)).astype(np.float32)
+    s_lt = rng.uniform(0.5, 1.0, 40).astype(np.float32)
+    x[3, 5] = 2.0                   # outside the bound
+    x[7, 33] = np.nan               # non-finite feature
+    net.set_guard(np.full(R.IN, -1.0, np.float32), np.full(R.IN, 1.0, np.float32), 1e6)
+    xd, sd = torch.from_numpy(x).cuda(), torch.from_numpy(s_lt).cuda()
+    delta = net.infer(xd).cpu().numpy()
+    out, nf = net.correct(xd, sd)
+    out = out.cpu().numpy()
+    assert int(nf.cpu()[0]) == 2
+    bad = np.zeros(40, bool)
+    bad[[3, 7]] = True
+    np.testing.assert_array_equal(out[bad], s_lt[bad])
+    np.testing.assert_array_equal(out[~bad], (s_lt + delta)[~bad])
+    net.set_guard(np.full(R.IN, -1.0, np.float32), np.full(R.IN, 1.0, np.float32), 0.0)
+    out, nf = net.correct(xd, sd)
+    assert int(nf.cpu()[0]) == 40 - int(np.sum((delta == 0) & ~bad))
+
+
+def test_features_match_oracle(gpu):
+    """Histogram fractions to FP32 rounding (same integer bin rule), log V to a few
+    ulp, mean LT / V^(1/3) within the 1e-5 bound of the measures."""
+    torch, lt = gpu
+    vol = synth.cfg4_volume(0, n_volumes=4, edges=(64, 96), counts=(8, 20))[0]
+    _note(f"features volume {vol.shape} labels={int(vol.max())}")
+    lab = np.asarray(vol).astype(np.int32)
+    D = O.edt_sq(lab)
+    LT = O.local_thickness_sq(D)
+    ml = int(lab.max())
+    sums = O.object_sums(lab, LT, ml)
+    cf = O.closed_forms(sums, 3)
+    hist = O.lt_histogram(lab, LT, sums["max_lt_sq"])
+    V = sums["volume"].astype(np.float64)
+    ok = V > 0
+    t = torch.from_numpy(vol).cuda()
+    _, _, m = lt.measure(t, ml, hist=True)
+    x = lt.mlp_features(m).cpu().double().numpy()
+    lt.default_context().sync_status()
+    np.testing.assert_allclose(x[:, :32][ok], hist[ok], rtol=2e-7, atol=0)
+    np.testing.assert_allclose(x[ok, 32], np.log(V[ok]), rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(x[ok, 33], cf["mean_lt"][ok] / np.cbrt(V[ok]), rtol=1e-5)
+    assert not np.all(np.isfinite(x[~ok]))
+
+
+# ------------------------------------------------------------------ learning gain
+
+
+def _dataset():
+    if not os.path.exists(DATASET):
+        pytest.skip("learned-correction data set not generated")
+    z = np.load(DATASET)
+    x = np.concatenate([z["hist"].astype(np.float32), z["extra"].astype(np.float32)], axis=1)
+    return x, z["s_lt"].astype(np.float64), z["s_mesh"].astype(np.float64), z["kind"]
+
+
+def fit_correction(torch, lt, x, s_lt, s_mesh, epochs=40, batch=256, lr=2e-3, seed=0):
+    """Standardise, train with a cosine learning-rate schedule, set the guard from the
+    training ranges."""
+    delta = s_mesh - s_lt
+    shift, scale = float(delta.mean()), float(delta.std())
+    mean, std = x.mean(axis=0), x.std(axis=0)
+    net = lt.MLP(seed=seed)
+    net.set_normalization(mean.astype(np.float32), std.astype(np.float32), shift, scale)
+    y = ((delta - shift) / scale).astype(np.float32)
+    n = (len(x) // batch) * batch
+    steps = epochs * (n // batch)
+    rng = np.random.default_rng(seed)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    k = 0
+    for _ in range(epochs):
+        perm = torch.from_numpy(rng.permutation(len(x))[:n]).cuda()
+        for j in range(0, n, batch):
+            idx = perm[j:j + batch]
+            lr_k = lr * 0.5 * (1 + math.cos(math.pi * k / steps))
+            net.train_step(xd[idx], yd[idx], lr=lr_k, weight_decay=1e-4)
+            k += 1
+    net.set_guard(x.min(axis=0).astype(np.float32), x.max(axis=0).astype(np.float32),
+                  float(np.abs(delta).max()))
+    return net
+
+
+def test_learned_correction_beats_closed_form(gpu):
+    torch, lt = gpu
+    x, s_lt, s_mesh, kind = _dataset()
+    held = np.arange(len(x)) % 5 == 0
+    _note(f"training on {int((~held).sum())} objects, held out {int(held.sum())}")
+    net = fit_correction(torch, lt, x[~held], s_lt[~held], s_mesh[~held])
+    xh = torch.from_numpy(x[held]).cuda()
+    sh = torch.from_numpy(s_lt[held].astype(np.float32)).cuda()
+    s_corr, nf = net.correct(xh, sh)
+    s_corr = s_corr.cpu().double().numpy()
+    coef = np.polyfit(s_lt[~held], s_mesh[~held], 1)                # affine recalibration
+    e_cf = np.abs(s_lt[held] - s_mesh[held]).mean()
+    e_aff = np.abs(np.polyval(coef, s_lt[held]) - s_mesh[held]).mean()
+    e_net = np.abs(s_corr - s_mesh[held]).mean()
+    _note(f"held-out MAE: closed form {e_cf:.4f}, affine {e_aff:.4f}, network {e_net:.4f}, "
+          f"fallbacks {int(nf.cpu()[0])}")
+    assert int(nf.cpu()[0]) <= 0.01 * held.sum()
+    # the network removes most of the closed form's error and beats the best affine
+    # recalibration of the closed form fitted on the same training objects
+    assert e_net < 0.3 * e_cf
+    assert e_net < 0.95 * e_aff
