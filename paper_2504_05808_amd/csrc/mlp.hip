@@ -221,7 +221,7 @@ struct Act {
 static size_t act_bytes(int cap) {
     const size_t c = (size_t)cap;
     return c * (MLP_INP + 3 * MLP_H + MLP_OUTP + 3 * MLP_H) * 2 +
-           c * (3 * MLP_H + MLP_OUTP + 2 * MLP_H + 3) * 4 + 16 * 256;
+           c * (3 * MLP_H + MLP_OUTP + 2 * MLP_H + 3) * 4 + 32 * 256;   // + per-array alignment slack
 }
 
 static Act act_layout(char* base, int cap) {
