@@ -3,8 +3,9 @@
 Workload (default): a 512^3 uint16 label volume with ~2000 superellipsoids
 (semi-axes U[4,30], exponents U[0.3,1], value-noise surface perturbation), the
 synthetic stand-in for the paper's labelled micro-CT volume.  A step is one pass of
-the whole path over the resident volume: lt_edt -> lt_thickness ->
-lt_object_measures.  Prints one JSON line.
+the whole path over the resident volume (lt_pipeline: EDT, local thickness with
+the per-object sums fused into its paint pass, closed forms).  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -37,8 +38,8 @@ def kernel_bytes(name: str, n: int, f: float, label_bytes: int = 2) -> float | N
         "edt_pass_y": (2 + lb + 4) * n,             # g, labels -> d2
         "edt_pass_z": (4 + lb + 4) * n,             # d2, labels -> D
         "bbox_runs": lb * n,                        # labels
-        "prune3d": (lb + 4) * n + 4 * f * n,        # labels, D -> kept-centre field of object voxels
-        "fronts3d": 4 * f * n + 16 * f * n + 4 * (1 - f) * n,   # kept field -> 4 front planes; LT = 0 outside
+        "prune3d": 4 * n + lb * f * n + 4 * n + 4 * (1 - f) * n,   # D, object labels -> kept field; LT = 0 outside
+        "fronts3d": 4 * n + 16 * f * n,             # kept field -> 4 front planes of object voxels
         "paint_tiles": (lb + 16 + 4) * f * n,       # labels + fronts of object voxels -> LT
         "object_sums": (lb + 4) * n,                # labels + LT
     }
@@ -107,6 +108,44 @@ def copy_calibration(dev, nbytes: int = 1 << 30):
     b.copy_(a)
     torch.cuda.synchronize()
     print(f"# copy calibration: {nbytes} bytes read and written", flush=True)
+
+
+# Source files that define each kernel family; a recorded HBM-counter figure is used
+# only while these files (comments and blank space removed) are unchanged.
+KERNEL_SOURCES = {
+    "edt": ("paper_2504_05808_amd/csrc/edt.hip", "paper_2504_05808_amd/csrc/lt_internal.h"),
+    "thickness": ("paper_2504_05808_amd/csrc/thickness.hip", "paper_2504_05808_amd/csrc/lt_internal.h"),
+    "measures": ("paper_2504_05808_amd/csrc/measures.hip", "paper_2504_05808_amd/csrc/lt_internal.h"),
+}
+KERNEL_FAMILY = {"edt_pass_x": "edt", "edt_pass_y": "edt", "edt_pass_z": "edt", "bbox_runs": "thickness",
+                 "prune3d": "thickness", "fronts3d": "thickness", "paint_tiles": "thickness",
+                 "object_sums": "measures"}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_512cube.json")
+
+
+def source_digest(family: str) -> str:
+    import hashlib
+    import re
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES[family]:
+        text = open(os.path.join(ROOT, rel)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", "", text).encode())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch from the recorded FETCH_SIZE / WRITE_SIZE runs, scaled by
+    the copy calibration, or None when absent or taken on other kernel sources."""
+    fam = KERNEL_FAMILY.get(kernel)
+    if fam is None or not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = json.load(open(COUNTERS_FILE))
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("source_digest", {}).get(fam) != source_digest(fam):
+        return None
+    cal = rec["calibration"]
+    return k["fetch_kib"] * 1024 * cal["fetch_scale"] + k["write_kib"] * 1024 * cal["write_scale"]
 
 
 def cpu_baseline(vol: np.ndarray, seconds: float, threads: int) -> dict:
@@ -337,9 +376,7 @@ def main():
         copy_calibration(dev)
 
     def step():
-        lt.edt(lab, out=d, ctx=ctx)
-        lt.thickness(lab, d, max_label, out=t, ctx=ctx)
-        lt.object_measures(lab, t, max_label, out=m, ctx=ctx)
+        lt.pipeline(lab, max_label, out=(d, t, m), ctx=ctx)
 
     for _ in range(args.warmup):
         step()
@@ -376,7 +413,7 @@ def main():
         ops = 2.0 * work                             # a compare and a max per covered point
         ach = ops / (dom_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                "unit": "Tops/s", "frac": round(ach / ALU_PEAK_TOPS, 4), "traffic": None,
+                "unit": "Tops/s", "frac": round(ach / ALU_PEAK_TOPS, 4), "traffic": recorded_traffic(dom),
                 "work_per_launch": ops, "avg_ms": round(dom_ms, 4),
                 "note": "ball-cover work: 2 x sum over kept centres of |B(x)| (compare + max per "
                         "covered lattice point) / kernel time; peak = 32-bit VALU lanes x clock"}
@@ -385,7 +422,7 @@ def main():
         if b is not None:
             ach = b / (dom_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom),
                     "bytes_per_launch": b, "avg_ms": round(dom_ms, 4)}
     stage = {"edt": 0.0, "thickness": 0.0, "measures": 0.0}
     for k, v in kernels.items():

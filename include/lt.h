@@ -121,6 +121,17 @@ lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, in
                              const int64_t* shape, const int32_t* lt_sq, uint32_t max_label,
                              const lt_measures* out, void* stream);
 
+/* The whole path in one call: lt_edt, lt_thickness and lt_object_measures with
+ * the per-object sums accumulated while the local thickness is written (every
+ * object voxel is painted once, by a work item of its own object), so the
+ * separate reduction pass over the volume is skipped.  Outputs are those of the
+ * three calls, bit for bit.  dist_sq and lt_sq are device arrays of the volume's
+ * size; the context's scratch grows to hold the thickness and measures state
+ * together. */
+lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                      uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
+                      void* stream);
+
 /* Closed forms alone, from per-object sums held on the device (the last step of
  * lt_object_measures; exposed for callers that accumulate their own sums):
  *   mean_lt = sum_lt_q23 / 2^23 / volume, shell_mean_lt = shell_sum_q23 / 2^23 /

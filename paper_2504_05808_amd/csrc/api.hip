@@ -46,11 +46,26 @@ lt_status ensure_scratch(lt_ctx* ctx, size_t bytes) {
     return LT_OK;
 }
 
+size_t pipeline_measures_offset(const Geom& g, uint32_t max_label) {
+    return (thickness_scratch_bytes(g, max_label) + 255) & ~size_t(255);
+}
+
 size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label) {
     size_t b = edt_scratch_bytes(g);
-    b = std::max(b, thickness_scratch_bytes(g, max_label));
-    b = std::max(b, measures_scratch_bytes(max_label));
+    b = std::max(b, pipeline_measures_offset(g, max_label) + measures_scratch_bytes(max_label));
     return (b + 255) & ~size_t(255);
+}
+
+lt_status launch_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
+                          int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out, void* scratch,
+                          hipStream_t s) {
+    void* mscr = (char*)scratch + pipeline_measures_offset(g, max_label);
+    lt_status st = g.n > 0 ? launch_edt(ctx, labels, dt, g, dist_sq, scratch, s) : LT_OK;
+    MeasureSums sums;
+    if (!st) st = launch_measures_zero(ctx, max_label, out, mscr, s, &sums);
+    if (!st && g.n > 0) st = launch_thickness(ctx, labels, dt, g, dist_sq, max_label, lt_sq, scratch, s, &sums);
+    if (!st) st = launch_measures_finish(ctx, labels, dt, g, lt_sq, max_label, out, mscr, s);
+    return st;
 }
 
 lt_status geom_from(int ndim, const int64_t* shape, Geom* g) {
@@ -233,6 +248,22 @@ lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, in
     if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
     if ((st = ensure_scratch(ctx, measures_scratch_bytes(max_label)))) return st;
     return launch_measures(ctx, labels, dtype, g, lt_sq, max_label, out, ctx->scratch.ptr,
+                           (hipStream_t)stream);
+}
+
+lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                      uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
+                      void* stream) {
+    Geom g;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st) return st;
+    if (!out || !out->volume || !out->shell_count || !out->max_lt_sq || !out->mean_lt ||
+        !out->shell_mean_lt || !out->sphericity || !out->roundness)
+        return set_error(LT_E_ARG, "an output array of lt_measures is NULL");
+    if (g.n > 0 && (!dist_sq || !lt_sq)) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    if ((st = ensure_scratch(ctx, pipeline_scratch_bytes(g, max_label)))) return st;
+    return launch_pipeline(ctx, labels, dtype, g, max_label, dist_sq, lt_sq, out, ctx->scratch.ptr,
                            (hipStream_t)stream);
 }
 

@@ -159,9 +159,7 @@ lt_status lt_autotune(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
                 void* scr = ctx->scratch.ptr;
                 double ms = 0.0;
                 st = time_runs([&]() -> lt_status {
-                    lt_status r = launch_edt(ctx, labels, dtype, g, dist, scr, s);
-                    if (!r) r = launch_thickness(ctx, labels, dtype, g, dist, max_label, ltq, scr, s);
-                    if (!r) r = launch_measures(ctx, labels, dtype, g, ltq, max_label, &m, scr, s);
+                    lt_status r = launch_pipeline(ctx, labels, dtype, g, max_label, dist, ltq, &m, scr, s);
                     return r;
                 }, repeats > 0 ? repeats : 3, s, &ms);
                 if (st) break;

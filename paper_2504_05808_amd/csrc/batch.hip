@@ -28,12 +28,9 @@ struct lt_batch {
 
 namespace lt {
 
-static lt_status launch_pipeline(lt_ctx* ctx, const lt_volume& v, lt_dtype dt, const Geom& g,
-                                 void* scratch, hipStream_t s) {
-    lt_status st = launch_edt(ctx, v.labels, dt, g, v.dist_sq, scratch, s);
-    if (!st) st = launch_thickness(ctx, v.labels, dt, g, v.dist_sq, v.max_label, v.lt_sq, scratch, s);
-    if (!st) st = launch_measures(ctx, v.labels, dt, g, v.lt_sq, v.max_label, &v.measures, scratch, s);
-    return st;
+static lt_status launch_volume(lt_ctx* ctx, const lt_volume& v, lt_dtype dt, const Geom& g, void* scratch,
+                               hipStream_t s) {
+    return launch_pipeline(ctx, v.labels, dt, g, v.max_label, v.dist_sq, v.lt_sq, &v.measures, scratch, s);
 }
 
 static lt_status check_volume(const lt_volume& v, Geom* g) {
@@ -160,7 +157,7 @@ lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n, lt_dtype dt
         if ((st = hip_check(hipStreamWaitEvent(ls[k], ev[lanes], 0), "fork wait"))) return fail(st);
         void* scr = (char*)b->scratch + lane_off[k];
         for (int i : lane_vols[k])
-            if (geo[i].n > 0 && (st = launch_pipeline(ctx, vols[i], dtype, geo[i], scr, ls[k])))
+            if (geo[i].n > 0 && (st = launch_volume(ctx, vols[i], dtype, geo[i], scr, ls[k])))
                 return fail(st);
         if ((st = hip_check(hipEventRecord(ev[k], ls[k]), "join record"))) return fail(st);
         if ((st = hip_check(hipStreamWaitEvent(origin, ev[k], 0), "join wait"))) return fail(st);

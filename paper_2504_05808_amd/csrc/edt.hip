@@ -81,17 +81,22 @@ edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, 
 
 // One line pass along y (AXIS = 1, input g, squared here) or z (AXIS = 2, input d2).
 // A block owns 64 consecutive x and LINE_T consecutive positions along the pass
-// axis; it stages labels and values of those positions plus LINE_H on each side in
-// LDS (coalesced row loads), and each voxel's outward search reads LDS.  A search
-// that runs past the staged range continues with global loads (exact either way).
+// axis; it stages the values of those positions plus LINE_H on each side in LDS
+// (coalesced row loads), each packed with two run-boundary bits: LINE_BLK_DN when
+// the position's label differs from the next one's (a search walking down from
+// the next position stops there), LINE_BLK_UP when it differs from the previous
+// one's; positions outside the image count as background.  Each voxel's outward
+// search then reads one LDS word per step and direction.  A search that runs past
+// the staged range continues with global loads (exact either way).
 constexpr int LINE_T = 64, LINE_H = 32, LINE_ROWS = LINE_T + 2 * LINE_H;
+constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LINE_BLK_UP - 1u;
 
 template <typename L, int AXIS, typename F>
 __global__ void __launch_bounds__(512)
 edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __restrict__ out,
               int nx, int ny, int nz) {
     __shared__ L s_lab[LINE_ROWS * 64];
-    __shared__ int32_t s_val[LINE_ROWS * 64];
+    __shared__ uint32_t s_val[LINE_ROWS * 64];
     const int tx = threadIdx.x, ty = threadIdx.y;          // 64 x 8
     const int x = blockIdx.x * 64 + tx;
     const int n = AXIS == 1 ? ny : nz;
@@ -110,7 +115,14 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             fv = (int)f[i];
         }
         s_lab[r * 64 + tx] = lv;
-        s_val[r * 64 + tx] = AXIS == 1 ? fv * fv : fv;
+        s_val[r * 64 + tx] = (uint32_t)(AXIS == 1 ? fv * fv : fv);
+    }
+    __syncthreads();
+    for (int r = ty; r < LINE_ROWS; r += 8) {
+        const L lv = s_lab[r * 64 + tx];
+        const bool dn = r + 1 >= LINE_ROWS || s_lab[(r + 1) * 64 + tx] != lv;
+        const bool up = r == 0 || s_lab[(r - 1) * 64 + tx] != lv;
+        s_val[r * 64 + tx] |= (dn ? LINE_BLK_DN : 0u) | (up ? LINE_BLK_UP : 0u);
     }
     __syncthreads();
     if (x >= nx) return;
@@ -123,26 +135,62 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             out[i] = 0;
             continue;
         }
-        int best = s_val[r * 64 + tx];
+        const uint32_t w0 = s_val[r * 64 + tx];
+        int best = (int)(w0 & LINE_VAL);
         bool dlo = true, dhi = true;
         int k = 1;
+        // staged range, four steps per round: the eight words are loaded first so
+        // that their latencies overlap; the steps are then applied in order
+        while (k * k < best && (dlo || dhi) && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
+            uint32_t wl[4], wh[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                wl[u] = s_val[(r - k - u) * 64 + tx];
+                wh[u] = s_val[(r + k + u) * 64 + tx];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kk = (k + u) * (k + u);
+                if (kk < best) {
+                    if (dlo) {
+                        if (wl[u] & LINE_BLK_DN) {               // label(p-k) != label(p-k+1)
+                            best = min(best, kk);
+                            dlo = false;
+                        } else {
+                            best = min(best, kk + (int)(wl[u] & LINE_VAL));
+                        }
+                    }
+                    if (dhi) {
+                        if (wh[u] & LINE_BLK_UP) {               // label(p+k) != label(p+k-1)
+                            best = min(best, kk);
+                            dhi = false;
+                        } else {
+                            best = min(best, kk + (int)(wh[u] & LINE_VAL));
+                        }
+                    }
+                }
+            }
+            k += 4;
+        }
         for (; k * k < best && (dlo || dhi); ++k) {
             if (r - k < 0 || r + k >= LINE_ROWS) break;           // leave the staged range
             const int kk = k * k;
             if (dlo) {
-                if (p - k < 0 || s_lab[(r - k) * 64 + tx] != l) {
+                const uint32_t w = s_val[(r - k) * 64 + tx];
+                if (w & LINE_BLK_DN) {
                     best = min(best, kk);
                     dlo = false;
                 } else {
-                    best = min(best, kk + s_val[(r - k) * 64 + tx]);
+                    best = min(best, kk + (int)(w & LINE_VAL));
                 }
             }
             if (dhi) {
-                if (p + k >= n || s_lab[(r + k) * 64 + tx] != l) {
+                const uint32_t w = s_val[(r + k) * 64 + tx];
+                if (w & LINE_BLK_UP) {
                     best = min(best, kk);
                     dhi = false;
                 } else {
-                    best = min(best, kk + s_val[(r + k) * 64 + tx]);
+                    best = min(best, kk + (int)(w & LINE_VAL));
                 }
             }
         }

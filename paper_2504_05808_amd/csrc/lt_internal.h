@@ -32,14 +32,20 @@ constexpr int PAINT_THREADS = 1024;
 constexpr int ROW_MAX_CHUNKS = 32;
 
 // Packed z-front entry (3D): bits 0..18 D of the centre, 19..28 dz + 512 (dz is
-// the slice minus the centre's z), 29..31 (plane 0 only) number of entries, 7 =
-// more than ZF_PLANES (the column is rescanned).
+// the slice minus the centre's z), 29..31 (plane 0 only) number of entries.  The
+// count 7 marks a front longer than ZF_PLANES: with ZF_SPILL set, bits 16..23 hold
+// its length and bits 0..15 its offset in the spill region of the front pass's
+// block that owns the voxel; without it, the column is rescanned.
 constexpr uint32_t ZF_D_BITS = 19;
 constexpr uint32_t ZF_D_MASK = (1u << ZF_D_BITS) - 1u;
 constexpr uint32_t ZF_DZ_SHIFT = 19;
 constexpr uint32_t ZF_DZ_MASK = 1023u;
 constexpr uint32_t ZF_N_SHIFT = 29;
 constexpr int ZF_PLANES = 4;
+constexpr uint32_t ZF_SPILL = 1u << 28;
+// Spill words per (64 x 4 column block, slice) of the front pass: a quarter word per
+// voxel; a block whose long fronts need more falls back to rescans.
+constexpr int SPILL_PER_SLICE = 64;
 
 // Column-list entry (3D): (D << 11) | z.
 constexpr uint32_t CL_Z_BITS = 11;
@@ -108,15 +114,36 @@ lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g
                      int32_t* dist_sq, void* scratch, hipStream_t s);
 size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label);
 int paint_tile_rows(lt_ctx* ctx);
+// Device arrays of the per-object integer sums (zeroed by launch_measures_zero).
+struct MeasureSums {
+    uint64_t* vol;
+    uint64_t* shc;
+    int32_t* mx;
+    uint64_t* sq;
+    uint64_t* ssq;
+};
+// With `sums` set, the paint pass also accumulates the per-object sums of the
+// measures (the fused form); launch_measures_finish then completes them.
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           void* scratch, hipStream_t s);
+                           void* scratch, hipStream_t s, const MeasureSums* sums = nullptr);
 size_t measures_scratch_bytes(uint32_t max_label);
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                           const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
                           void* scratch, hipStream_t s);
-// Scratch for a whole pipeline (EDT, thickness, measures run in turn).
+lt_status launch_measures_zero(lt_ctx* ctx, uint32_t max_label, const lt_measures* out, void* scratch,
+                               hipStream_t s, MeasureSums* sums);
+lt_status launch_measures_finish(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                                 const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
+                                 void* scratch, hipStream_t s);
+// Scratch for the fused pipeline: EDT, then thickness with the measures' scratch
+// placed after the thickness region (both live during the paint pass).
 size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label);
+size_t pipeline_measures_offset(const Geom& g, uint32_t max_label);
+// EDT -> thickness with fused sums -> histogram and closed forms.
+lt_status launch_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
+                          int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out, void* scratch,
+                          hipStream_t s);
 lt_status launch_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q,
                               const int32_t* max_lt_sq, const uint64_t* shell_count,
                               const uint64_t* shell_sum_q, uint32_t n, int ndim,

@@ -12,7 +12,8 @@
 //
 // Sums of radii are accumulated in Q.23 fixed point in uint64, so results do not
 // depend on atomic order.  A wave reduces each run of equal labels among its 64
-// lanes (consecutive x) and issues one set of atomics per run.
+// lanes (consecutive x); blocks merge the runs of a 64 x 16 x 8 brick per label in
+// LDS before one set of global atomics per label and block.
 #include <math.h>
 
 #include "lt_internal.h"
@@ -43,62 +44,111 @@ __global__ void zero_measure_arrays(uint64_t* vol, uint64_t* shc, int32_t* mx, u
     ssq[l] = 0;
 }
 
+constexpr int SUM_TAB = 64;                  // labels per block table
+constexpr int SUM_BY = 16, SUM_BZ = 8;       // block brick: 64 (x) x SUM_BY (y) x SUM_BZ (z)
+
+// Label table slot (open addressing, linear probing, key 0 = empty); -1 if full.
+__device__ __forceinline__ int sum_slot(uint32_t* keys, uint32_t l) {
+    int h = (int)((l * 2654435761u) >> 7) & (SUM_TAB - 1);
+    for (int probe = 0; probe < SUM_TAB; ++probe) {
+        const uint32_t k = atomicCAS(&keys[h], 0u, l);
+        if (k == 0u || k == l) return h;
+        h = (h + 1) & (SUM_TAB - 1);
+    }
+    return -1;
+}
+
+// One block per 64 x 16 x 8 brick.  Per slice, each wave (one 64-voxel row segment)
+// reduces every run of equal labels among its lanes; the run's lead lane merges the
+// totals into the block's label table with LDS atomics (global atomics if the table
+// is full); the table is flushed to global memory once per block.
 template <int NDIM, typename L>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, int ny, int nz,
             uint32_t max_label, uint64_t* __restrict__ vol, uint64_t* __restrict__ shc,
             int32_t* __restrict__ mx, uint64_t* __restrict__ sq, uint64_t* __restrict__ ssq,
             uint32_t* err) {
-    // blocks of 64 (x) x 4 (y): each wave is one row segment, and the rows above and
-    // below that the shell test reads are loaded by the same block
+    __shared__ uint32_t s_key[SUM_TAB];
+    __shared__ unsigned long long s_vol[SUM_TAB], s_shc[SUM_TAB], s_sq[SUM_TAB], s_ssq[SUM_TAB];
+    __shared__ int s_mx[SUM_TAB];
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    if (tid < SUM_TAB) {
+        s_key[tid] = 0u;
+        s_vol[tid] = s_shc[tid] = s_sq[tid] = s_ssq[tid] = 0ull;
+        s_mx[tid] = 0;
+    }
+    __syncthreads();
     const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int y = blockIdx.y * SUM_BY + threadIdx.y;
     const size_t plane = (size_t)ny * nx;
-  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
-    const size_t i = (size_t)z * plane + (size_t)y * nx + x;
-    uint64_t l = 0;
-    int v = 0;
-    bool shell = false;
-    uint64_t q = 0;
-    if (x < nx && y < ny) {
-        const L raw = lab[i];
-        if (raw != 0) {
-            if (label_negative(raw) || (uint64_t)raw > max_label) {
-                atomicOr(err, ERR_LABEL);
-            } else {
-                l = (uint64_t)raw;
-                v = lt[i];
-                q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
-                shell = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 ||
-                        lab[i - 1] != raw || lab[i + 1] != raw || lab[i - nx] != raw ||
-                        lab[i + nx] != raw;
-                if (NDIM == 3 && !shell)
-                    shell = z == 0 || z == nz - 1 || lab[i - plane] != raw || lab[i + plane] != raw;
+    const int z0 = blockIdx.z * SUM_BZ, z1 = min(nz, z0 + SUM_BZ);
+    for (int z = z0; z < z1; ++z) {
+        const size_t i = (size_t)z * plane + (size_t)y * nx + x;
+        uint32_t l = 0;
+        int v = 0;
+        bool shell = false;
+        uint64_t q = 0;
+        if (x < nx && y < ny) {
+            const L raw = lab[i];
+            if (raw != 0) {
+                if (label_negative(raw) || (uint64_t)raw > max_label) {
+                    atomicOr(err, ERR_LABEL);
+                } else {
+                    l = (uint32_t)raw;
+                    v = lt[i];
+                    q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
+                    shell = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 ||
+                            lab[i - 1] != raw || lab[i + 1] != raw || lab[i - nx] != raw ||
+                            lab[i + nx] != raw;
+                    if (NDIM == 3 && !shell)
+                        shell = z == 0 || z == nz - 1 || lab[i - plane] != raw || lab[i + plane] != raw;
+                }
             }
         }
-    }
-    uint64_t active = __ballot(l != 0);
-    while (active) {
-        const int lead = __ffsll((unsigned long long)active) - 1;
-        const uint64_t L0 = (uint64_t)__shfl((unsigned long long)l, lead, 64);
-        const bool in = (l == L0);
-        const uint64_t m = __ballot(in);
-        const uint64_t sm = __ballot(in && shell);
-        const uint64_t s1 = wave_sum_u64(in ? q : 0);
-        const uint64_t s2 = wave_sum_u64(in && shell ? q : 0);
-        const int m1 = wave_max_i32(in ? v : 0);
-        if ((int)threadIdx.x == lead) {
-            atomicAdd((unsigned long long*)&vol[L0], (unsigned long long)__popcll(m));
-            atomicAdd((unsigned long long*)&sq[L0], (unsigned long long)s1);
-            atomicMax(&mx[L0], m1);
-            if (sm) {
-                atomicAdd((unsigned long long*)&shc[L0], (unsigned long long)__popcll(sm));
-                atomicAdd((unsigned long long*)&ssq[L0], (unsigned long long)s2);
+        uint64_t active = __ballot(l != 0);
+        while (active) {
+            const int lead = __ffsll((unsigned long long)active) - 1;
+            const uint32_t L0 = (uint32_t)__shfl((int)l, lead, 64);
+            const bool in = (l == L0);
+            const uint64_t m = __ballot(in);
+            const uint64_t sm = __ballot(in && shell);
+            const uint64_t s1 = wave_sum_u64(in ? q : 0);
+            const uint64_t s2 = wave_sum_u64(in && shell ? q : 0);
+            const int m1 = wave_max_i32(in ? v : 0);
+            if ((int)threadIdx.x == lead) {
+                const int slot = sum_slot(s_key, L0);
+                if (slot >= 0) {
+                    atomicAdd(&s_vol[slot], (unsigned long long)__popcll(m));
+                    atomicAdd(&s_sq[slot], (unsigned long long)s1);
+                    atomicMax(&s_mx[slot], m1);
+                    if (sm) {
+                        atomicAdd(&s_shc[slot], (unsigned long long)__popcll(sm));
+                        atomicAdd(&s_ssq[slot], (unsigned long long)s2);
+                    }
+                } else {
+                    atomicAdd((unsigned long long*)&vol[L0], (unsigned long long)__popcll(m));
+                    atomicAdd((unsigned long long*)&sq[L0], (unsigned long long)s1);
+                    atomicMax(&mx[L0], m1);
+                    if (sm) {
+                        atomicAdd((unsigned long long*)&shc[L0], (unsigned long long)__popcll(sm));
+                        atomicAdd((unsigned long long*)&ssq[L0], (unsigned long long)s2);
+                    }
+                }
             }
+            active &= ~m;
         }
-        active &= ~m;
     }
-  }
+    __syncthreads();
+    if (tid < SUM_TAB && s_key[tid] != 0u) {
+        const uint32_t L0 = s_key[tid];
+        atomicAdd((unsigned long long*)&vol[L0], s_vol[tid]);
+        atomicAdd((unsigned long long*)&sq[L0], s_sq[tid]);
+        atomicMax(&mx[L0], s_mx[tid]);
+        if (s_shc[tid]) {
+            atomicAdd((unsigned long long*)&shc[L0], s_shc[tid]);
+            atomicAdd((unsigned long long*)&ssq[L0], s_ssq[tid]);
+        }
+    }
 }
 
 // Local-thickness histogram (32 bins of sqrt(LT_sq) / R, R^2 = the object's max):
@@ -204,50 +254,81 @@ __global__ void fill_u32(uint32_t* p, size_t n) {
         p[i] = 0u;
 }
 
-template <typename L>
-static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
-                                uint32_t max_label, const lt_measures* out, void* scratch,
-                                hipStream_t s) {
-    const size_t nlab = (size_t)max_label + 1;
+// Per-object accumulators in the caller's scratch: Q.23 radius sums of all and of
+// shell voxels, then the histogram counts.
+struct MeasureScratch {
+    uint64_t *sq, *ssq;
+    uint32_t* hist;
+};
+
+static MeasureScratch measure_scratch(void* scratch, size_t nlab) {
     char* base = (char*)scratch;
-    uint64_t* sq = (uint64_t*)base;
-    uint64_t* ssq = (uint64_t*)(base + align256(nlab * sizeof(uint64_t)));
-    uint32_t* hist = (uint32_t*)(base + 2 * align256(nlab * sizeof(uint64_t)));
-    const unsigned lb = (unsigned)((nlab + 255) / 256);
+    MeasureScratch m;
+    m.sq = (uint64_t*)base;
+    m.ssq = (uint64_t*)(base + align256(nlab * sizeof(uint64_t)));
+    m.hist = (uint32_t*)(base + 2 * align256(nlab * sizeof(uint64_t)));
+    return m;
+}
+
+lt_status launch_measures_zero(lt_ctx* ctx, uint32_t max_label, const lt_measures* out, void* scratch,
+                               hipStream_t s, MeasureSums* sums) {
+    const size_t nlab = (size_t)max_label + 1;
+    const MeasureScratch m = measure_scratch(scratch, nlab);
     {
         ProfScope _p(ctx, s, "zero_measure_arrays");
-        zero_measure_arrays<<<lb, 256, 0, s>>>(out->volume, out->shell_count, out->max_lt_sq, sq, ssq,
-                                               (uint32_t)nlab);
+        zero_measure_arrays<<<(unsigned)((nlab + 255) / 256), 256, 0, s>>>(out->volume, out->shell_count,
+                                                                          out->max_lt_sq, m.sq, m.ssq,
+                                                                          (uint32_t)nlab);
     }
-    if (g.n > 0) {
-        ProfScope _p(ctx, s, "object_sums");
-        const long b2 = (long)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
-        const dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, loop_extent(g.nz, b2, ctx, 1 << 20)), blk(64, 4);
-        if (g.ndim == 3)
-            object_sums<3, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, g.nz, max_label, out->volume,
-                                                   out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
-        else
-            object_sums<2, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, 1, max_label, out->volume,
-                                                   out->shell_count, out->max_lt_sq, sq, ssq, ctx->d_err);
-    }
+    if (sums) *sums = MeasureSums{out->volume, out->shell_count, out->max_lt_sq, m.sq, m.ssq};
+    return hip_check(hipGetLastError(), "measures launch");
+}
+
+template <typename L>
+static lt_status measures_finish_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
+                                       uint32_t max_label, const lt_measures* out, void* scratch,
+                                       hipStream_t s) {
+    const size_t nlab = (size_t)max_label + 1;
+    const MeasureScratch m = measure_scratch(scratch, nlab);
     if (out->hist32) {
         {
             ProfScope _p(ctx, s, "fill_u32");
-            fill_u32<<<(unsigned)min((size_t)4096, (nlab * 32 + 255) / 256), 256, 0, s>>>(hist, nlab * 32);
+            fill_u32<<<(unsigned)min((size_t)4096, (nlab * 32 + 255) / 256), 256, 0, s>>>(m.hist, nlab * 32);
         }
         if (g.n > 0) {
             ProfScope _p(ctx, s, "lt_histogram");
             lt_histogram<L><<<(unsigned)((g.n + 255) / 256), 256, 0, s>>>(lab, lt, g.n, max_label,
-                                                                         out->max_lt_sq, hist);
+                                                                         out->max_lt_sq, m.hist);
         }
     }
     {
         ProfScope _p(ctx, s, "closed_forms");
-        closed_forms_kernel<<<lb, 256, 0, s>>>(out->volume, sq, out->max_lt_sq, out->shell_count, ssq,
-                                               (uint32_t)nlab, g.ndim, out->mean_lt, out->shell_mean_lt,
-                                               out->sphericity, out->roundness, hist, out->hist32);
+        closed_forms_kernel<<<(unsigned)((nlab + 255) / 256), 256, 0, s>>>(
+            out->volume, m.sq, out->max_lt_sq, out->shell_count, m.ssq, (uint32_t)nlab, g.ndim, out->mean_lt,
+            out->shell_mean_lt, out->sphericity, out->roundness, m.hist, out->hist32);
     }
     return hip_check(hipGetLastError(), "measures launch");
+}
+
+template <typename L>
+static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
+                                uint32_t max_label, const lt_measures* out, void* scratch,
+                                hipStream_t s) {
+    MeasureSums sums;
+    lt_status st = launch_measures_zero(ctx, max_label, out, scratch, s, &sums);
+    if (st) return st;
+    if (g.n > 0) {
+        ProfScope _p(ctx, s, "object_sums");
+        const dim3 grid((g.nx + 63) / 64, (g.ny + SUM_BY - 1) / SUM_BY, (g.nz + SUM_BZ - 1) / SUM_BZ),
+            blk(64, SUM_BY);
+        if (g.ndim == 3)
+            object_sums<3, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, g.nz, max_label, sums.vol, sums.shc,
+                                                   sums.mx, sums.sq, sums.ssq, ctx->d_err);
+        else
+            object_sums<2, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, 1, max_label, sums.vol, sums.shc,
+                                                   sums.mx, sums.sq, sums.ssq, ctx->d_err);
+    }
+    return measures_finish_typed(ctx, lab, g, lt, max_label, out, scratch, s);
 }
 
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
@@ -257,6 +338,20 @@ lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Ge
         case LT_U16: return measures_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s);
         case LT_I32: return measures_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s);
         case LT_U32: return measures_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s);
+    }
+    return set_error(LT_E_DTYPE, "unknown dtype");
+}
+
+lt_status launch_measures_finish(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                                 const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
+                                 void* scratch, hipStream_t s) {
+    switch (dt) {
+        case LT_U16:
+            return measures_finish_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s);
+        case LT_I32:
+            return measures_finish_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s);
+        case LT_U32:
+            return measures_finish_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

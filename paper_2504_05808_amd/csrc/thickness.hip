@@ -16,13 +16,14 @@
 //     is covered by the dominating one in every later step.  A positive residual
 //     means the ball holds (z, y, x) itself, so every pair of a front belongs to
 //     the label of that voxel.  Fronts are computed by one thread per column walking
-//     z (coalesced across x) and stored in up to three dense planes.
+//     z (coalesced across x) and stored in up to four dense planes; a larger front
+//     is flagged and the paint pass rescans that column's kept centres.
 //  3. Disc painting.  In slice z, a front pair is a disc of squared radius b around
 //     (y, x) carrying value D; each disc row is an interval along x.  Intervals are
 //     max-painted into an LDS sparse table (two atomics per interval: the interval
 //     is covered by two blocks of length 2^k), and a push-down over the levels
 //     yields the per-voxel maximum.
-// Work items are (object, 32x64 tile of the object's y-x bounding box) and run
+// Work items are (object, 64x64 or 32x64 tile of the object's y-x bounding box) and run
 // slice by slice over the object's z extent; the source columns of a tile are the
 // tile grown by the object's largest ball reach, clipped to its bounding box.
 #include <mutex>
@@ -44,98 +45,106 @@ __global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uin
     maxd[l] = 0;
 }
 
-// Bounding boxes from runs along x, one block per row.  Ballots mark where runs end;
-// the first voxel of each run finds its end with bit scans (its own 64-wide chunk,
-// else the next chunks' end masks kept in LDS) and updates the six extrema of its
-// label.  bb layout: [zmin, zmax, ymin, ymax, xmin, xmax][nlab].
+// Per-block label table in LDS: open addressing with linear probing on the key
+// (label, 0 = empty).  Returns the slot of `l`, inserting it, or -1 when the table
+// is full (the caller then updates global memory directly).
+template <int CAP>
+__device__ __forceinline__ int lds_slot(uint32_t* keys, uint32_t l) {
+    int h = (int)((l * 2654435761u) >> 7) & (CAP - 1);
+    for (int probe = 0; probe < CAP; ++probe) {
+        const uint32_t k = atomicCAS(&keys[h], 0u, l);
+        if (k == 0u || k == l) return h;
+        h = (h + 1) & (CAP - 1);
+    }
+    return -1;
+}
+
+constexpr int BB_TAB = 128;           // labels per block table
+constexpr int BB_ROWS_Y = 16, BB_ROWS_Z = 8;
+
+// Bounding boxes from runs along x.  A block takes BB_ROWS_Y x BB_ROWS_Z rows; each
+// wave walks whole rows.  Per row, a first sweep ballots the run ends of every
+// 64-voxel chunk (lane c keeps chunk c's mask); a second sweep gives each run's
+// first voxel its end (its own chunk's mask, else the first later chunk with an
+// end) and merges (z, y, x_first, x_last) into the block's label table with LDS
+// atomics.  The table is flushed to the global boxes once per block.
+// bb layout: [zmin, zmax, ymin, ymax, xmin, xmax][nlab].
 template <typename L>
 __global__ void __launch_bounds__(1024)
 bbox_runs(const L* __restrict__ lab, int nx, int ny, int nz, uint32_t max_label, int32_t* bb,
           uint32_t nlab, uint32_t* err) {
-    __shared__ unsigned long long s_end[ROW_MAX_CHUNKS];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-    const int chunks = (nx + 63) >> 6;
-    const int y = blockIdx.y;
-  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
-    const L* r = lab + ((size_t)z * ny + y) * nx;
-    for (int c = wid; c < chunks; c += nw) {
-        const int x = c * 64 + lane;
-        bool en = false;
-        if (x < nx) en = x == nx - 1 || r[x + 1] != r[x];
-        const unsigned long long me = __ballot(en);
-        if (lane == 0) s_end[c] = me;
+    __shared__ uint32_t s_key[BB_TAB];
+    __shared__ int s_bb[6][BB_TAB];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < BB_TAB; t += blockDim.x) {
+        s_key[t] = 0u;
+        s_bb[0][t] = s_bb[2][t] = s_bb[4][t] = 0x7fffffff;
+        s_bb[1][t] = s_bb[3][t] = s_bb[5][t] = -1;
     }
     __syncthreads();
-    for (int c = wid; c < chunks; c += nw) {
-        const int x = c * 64 + lane;
-        if (x >= nx) continue;
-        const L l = r[x];
-        if (l == 0 || (x > 0 && r[x - 1] == l)) continue;
-        if (label_negative(l) || (uint64_t)l > max_label) {
-            atomicOr(err, ERR_LABEL);
-            continue;
+    const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    const int chunks = (nx + 63) >> 6;                   // <= 64
+    const int y0 = blockIdx.y * BB_ROWS_Y, z0 = blockIdx.z * BB_ROWS_Z;
+    const int rows = BB_ROWS_Y * BB_ROWS_Z;
+    for (int r = wid; r < rows; r += nw) {
+        const int y = y0 + r % BB_ROWS_Y, z = z0 + r / BB_ROWS_Y;
+        if (y >= ny || z >= nz) continue;                // wave-uniform
+        const L* row = lab + ((size_t)z * ny + y) * nx;
+        unsigned long long mine = 0ull;
+        for (int c = 0; c < chunks; ++c) {
+            const int x = c * 64 + lane;
+            const bool en = x < nx && (x == nx - 1 || row[x + 1] != row[x]);
+            const unsigned long long me = __ballot(en);
+            if (lane == c) mine = me;
         }
-        const unsigned long long above = s_end[c] & ~((1ull << lane) - 1ull);
-        int e;
-        if (above) {
-            e = c * 64 + __ffsll(above) - 1;
-        } else {
-            int cc = c + 1;
-            while (s_end[cc] == 0ull) ++cc;                // the last chunk ends at x = nx - 1
-            e = cc * 64 + __ffsll(s_end[cc]) - 1;
+        for (int c = 0; c < chunks; ++c) {
+            const int x = c * 64 + lane;
+            const L l = x < nx ? row[x] : (L)0;
+            bool start = l != 0 && (x == 0 || row[x - 1] != l);
+            const unsigned long long cm = __shfl(mine, c, 64);
+            const unsigned long long later = __ballot(lane > c && lane < chunks && mine != 0ull);
+            const int cc = later ? __ffsll(later) - 1 : c;
+            const unsigned long long nm = __shfl(mine, cc, 64);
+            if (!start) continue;
+            if (label_negative(l) || (uint64_t)l > max_label) {
+                atomicOr(err, ERR_LABEL);
+                continue;
+            }
+            const unsigned long long above = cm & ~((1ull << lane) - 1ull);
+            const int e = above ? c * 64 + __ffsll(above) - 1 : cc * 64 + __ffsll(nm) - 1;
+            const uint32_t u = (uint32_t)l;
+            const int slot = lds_slot<BB_TAB>(s_key, u);
+            if (slot >= 0) {
+                atomicMin(&s_bb[0][slot], z);
+                atomicMax(&s_bb[1][slot], z);
+                atomicMin(&s_bb[2][slot], y);
+                atomicMax(&s_bb[3][slot], y);
+                atomicMin(&s_bb[4][slot], x);
+                atomicMax(&s_bb[5][slot], e);
+            } else {
+                atomicMin(&bb[0 * nlab + u], z);
+                atomicMax(&bb[1 * nlab + u], z);
+                atomicMin(&bb[2 * nlab + u], y);
+                atomicMax(&bb[3 * nlab + u], y);
+                atomicMin(&bb[4 * nlab + u], x);
+                atomicMax(&bb[5 * nlab + u], e);
+            }
         }
-        const uint32_t u = (uint32_t)l;
-        atomicMin(&bb[0 * nlab + u], z);
-        atomicMax(&bb[1 * nlab + u], z);
-        atomicMin(&bb[2 * nlab + u], y);
-        atomicMax(&bb[3 * nlab + u], y);
-        atomicMin(&bb[4 * nlab + u], x);
-        atomicMax(&bb[5 * nlab + u], e);
     }
-    __syncthreads();                                     // the masks are reused by the next row
-  }
+    __syncthreads();
+    for (int t = tid; t < BB_TAB; t += blockDim.x) {
+        const uint32_t u = s_key[t];
+        if (u == 0u) continue;
+        atomicMin(&bb[0 * nlab + u], s_bb[0][t]);
+        atomicMax(&bb[1 * nlab + u], s_bb[1][t]);
+        atomicMin(&bb[2 * nlab + u], s_bb[2][t]);
+        atomicMax(&bb[3 * nlab + u], s_bb[3][t]);
+        atomicMin(&bb[4 * nlab + u], s_bb[4][t]);
+        atomicMax(&bb[5 * nlab + u], s_bb[5][t]);
+    }
 }
 
 // ------------------------------------------------------------------ Pareto fronts
-
-struct Front {
-    int v[ZF_PLANES], b[ZF_PLANES], dz[ZF_PLANES];
-    int n;
-    bool overflow;
-};
-
-__device__ __forceinline__ void front_clear(Front& f) {
-#pragma unroll
-    for (int i = 0; i < ZF_PLANES; ++i) f.v[i] = f.b[i] = f.dz[i] = 0;
-    f.n = 0;
-    f.overflow = false;
-}
-
-// Insert (v, b) unless dominated; drop entries it dominates.  Empty slots hold v = 0,
-// which no real pair (v >= 1) is dominated by.
-__device__ __forceinline__ void front_insert(Front& f, int v, int b, int dz) {
-    bool dom = false;
-#pragma unroll
-    for (int i = 0; i < ZF_PLANES; ++i) dom |= (f.v[i] >= v && f.b[i] >= b);
-    if (dom) return;
-#pragma unroll
-    for (int i = 0; i < ZF_PLANES; ++i)
-        if (f.v[i] != 0 && f.v[i] <= v && f.b[i] <= b) {
-            f.v[i] = 0;
-            f.b[i] = 0;
-        }
-    bool placed = false;
-#pragma unroll
-    for (int i = 0; i < ZF_PLANES; ++i)
-        if (!placed && f.v[i] == 0) {
-            f.v[i] = v;
-            f.b[i] = b;
-            f.dz[i] = dz;
-            placed = true;
-        }
-    if (!placed) f.overflow = true;
-}
 
 __device__ __forceinline__ uint32_t zf_pack(int v, int dz) {
     return (uint32_t)v | ((uint32_t)(dz + 512) << ZF_DZ_SHIFT);
@@ -174,52 +183,114 @@ max_over_labels(const int32_t* __restrict__ maxd, uint32_t nlab, uint32_t* __res
     if (threadIdx.x == 0) *gmax = (uint32_t)s[0];
 }
 
-// One thread per voxel (blocks of 64 x 4 voxels in x, y share neighbour rows in L1):
-// background LT = 0; a centre is kept unless a 26-neighbour's open ball contains
-// its ball; kd = D for kept centres, 0 elsewhere; per-label and global max D.
+// One thread per voxel: background LT = 0; a centre is kept unless a 26-neighbour's
+// open ball contains its ball; kd = D for kept centres, 0 elsewhere; per-label max
+// of the kept D (the global max follows in max_over_labels).
+constexpr int PR_TY = 8, PR_ZB = 16, PR_W = 66, PR_H = PR_TY + 2, PR_TAB = 64;
+
 template <typename L>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny, int nz,
         uint32_t max_label, const int32_t* __restrict__ tab, int32_t* __restrict__ kd,
         int32_t* __restrict__ lt, int32_t* __restrict__ maxd, uint32_t* err) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    // a block walks PR_ZB consecutive slices of a 64 x PR_TY tile; D of the slices
+    // below, at and above the current one (tile + 1 voxel halo) rotate through LDS
+    __shared__ int32_t s_d[3][PR_H][PR_W];
+    __shared__ uint32_t s_key[PR_TAB];
+    __shared__ int s_max[PR_TAB];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * PR_TY;
+    const int x = x0 + tx, y = y0 + ty;
     const bool inside = x < nx && y < ny;
     const size_t plane = (size_t)ny * nx;
-  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
-    const size_t i = inside ? (size_t)z * plane + (size_t)y * nx + x : 0;
-    const int d = inside ? D[i] : 0;
-    bool keep = false;
-    uint32_t l = 0;
-    if (d > 0) {
-        const L raw = lab[i];
-        keep = true;
-        if (d <= PRUNE_DCAP) {
-            const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d], a3 = tab[2 * (PRUNE_DCAP + 1) + d];
+    const int zs = blockIdx.z * PR_ZB, ze = min(nz, zs + PR_ZB);
+    if (tid < PR_TAB) {
+        s_key[tid] = 0u;
+        s_max[tid] = 0;
+    }
+    // each thread moves (at most) two words of a halo plane: loaded into registers
+    // one slice ahead, stored to LDS at the top of the next iteration
+    constexpr int PR_N = PR_H * PR_W;
+    int pv[2];
+    auto fetch = [&](int z) {
 #pragma unroll
-            for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int k = dz * dz + dy * dy + dx * dx;
-                        if (k == 0) continue;
-                        const bool inb = z + dz >= 0 && z + dz < nz && y + dy >= 0 && y + dy < ny &&
-                                         x + dx >= 0 && x + dx < nx;
-                        const int dn = inb ? D[(ptrdiff_t)i + dz * (ptrdiff_t)plane + dy * nx + dx] : 0;
-                        keep = keep && !(dn > (k == 1 ? a1 : (k == 2 ? a2 : a3)));
-                    }
+        for (int u = 0; u < 2; ++u) {
+            const int q = tid + u * 512;
+            const int hy = q / PR_W, hx = q - hy * PR_W;
+            const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+            pv[u] = (q < PR_N && z >= 0 && z < nz && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+                        ? D[(size_t)z * plane + (size_t)gy * nx + gx]
+                        : 0;
         }
-        if (keep && d > (int)ZF_D_MASK) atomicOr(err, ERR_OVERFLOW);
-        if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;   // flagged elsewhere
-        l = (uint32_t)raw;
+    };
+    auto store = [&](int z) {
+        const int slot = (z + 3) % 3;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int q = tid + u * 512;
+            if (q < PR_N) (&s_d[slot][0][0])[q] = pv[u];
+        }
+    };
+    fetch(zs - 1);
+    store(zs - 1);
+    fetch(zs);
+    store(zs);
+    fetch(zs + 1);
+    for (int z = zs; z < ze; ++z) {
+        store(z + 1);
+        __syncthreads();
+        fetch(z + 2);                                    // in flight while slice z is tested
+        const int sc = (z + 3) % 3;
+        const int d = inside ? s_d[sc][ty + 1][tx + 1] : 0;
+        const size_t i = inside ? (size_t)z * plane + (size_t)y * nx + x : 0;
+        bool keep = false;
+        uint32_t l = 0;
+        if (d > 0) {
+            const L raw = lab[i];
+            keep = true;
+            if (d <= PRUNE_DCAP) {
+                const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d], a3 = tab[2 * (PRUNE_DCAP + 1) + d];
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int sl = (z + dz + 3) % 3;
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int k = dz * dz + dy * dy + dx * dx;
+                            if (k == 0) continue;
+                            const int dn = s_d[sl][ty + 1 + dy][tx + 1 + dx];
+                            keep = keep && !(dn > (k == 1 ? a1 : (k == 2 ? a2 : a3)));
+                        }
+                }
+            }
+            if (keep && d > (int)ZF_D_MASK) atomicOr(err, ERR_OVERFLOW);
+            if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;   // flagged elsewhere
+            l = (uint32_t)raw;
+        }
+        if (inside) {
+            kd[i] = keep ? d : 0;
+            if (d <= 0) lt[i] = 0;
+        }
+        // per-label largest kept D: wave maxima merged in the block table
+        uint64_t active = __ballot(keep);
+        while (active) {
+            const int lead = __ffsll((unsigned long long)active) - 1;
+            const uint32_t L0 = (uint32_t)__shfl((int)l, lead, 64);
+            const bool in = keep && l == L0;
+            int m = in ? d : 0;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+            if (tx == lead) {
+                const int slot = lds_slot<PR_TAB>(s_key, L0);
+                if (slot >= 0) atomicMax(&s_max[slot], m);
+                else atomicMax(&maxd[L0], m);
+            }
+            active &= ~__ballot(in);
+        }
+        __syncthreads();                                 // the slot of z - 1 is reloaded next
     }
-    if (inside) {
-        kd[i] = keep ? d : 0;
-        if (d <= 0) lt[i] = 0;
-    }
-    wave_label_max(l, keep, d, maxd);
-  }
+    if (tid < PR_TAB && s_key[tid] != 0u) atomicMax(&maxd[s_key[tid]], s_max[tid]);
 }
 
 // ------------------------------------------------------------------ 3D z-fronts
@@ -228,20 +299,26 @@ constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
 
 // One thread per (column, chunk of `chunk` slices).  The kept centres of the
 // column within the chunk grown by the global reach R are gathered (batched loads)
-// into the thread's LDS list in z order; then for each slice of the chunk the
-// Pareto front over (value D, residual D - dz^2 > 0) of the centres within reach is
-// formed from a sliding window of that list and stored in the front planes.  A
-// list that would exceed FR_CAP marks the chunk's fronts as "rescan" (count 7);
-// the paint pass then takes every centre of the column instead (same result).
+// into the thread's LDS list and ordered by D; then for each slice of the chunk
+// one scan of that list yields the Pareto front over (value D, residual
+// D - dz^2 > 0), stored in the front planes or, when longer than the planes, in
+// the block's spill region.  A list that would exceed FR_CAP marks the chunk's
+// fronts as "rescan" (count 7); the paint pass then takes every centre of the
+// column instead (same result).
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
-         const uint32_t* __restrict__ gmax, uint32_t* __restrict__ zf) {
+         const uint32_t* __restrict__ gmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
     __shared__ uint32_t s_list[256 * FR_CAP];
+    __shared__ uint32_t s_used;                    // words of the block's spill region in use
     const int tid = threadIdx.y * 64 + threadIdx.x;
+    if (tid == 0) s_used = 0u;
+    __syncthreads();
     uint32_t* list = s_list + tid;                 // stride 256: lane-interleaved, no bank conflicts
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
+    const uint32_t cap = (uint32_t)(SPILL_PER_SLICE * chunk);
+    uint32_t* region = spill + ((size_t)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * cap;
     const int c0 = blockIdx.z * chunk, c1 = min(nz, c0 + chunk);
     const int R = open_reach(max((int)*gmax, 1));
     const int zlo = max(0, c0 - R), zhi = min(nz, c1 + R);
@@ -266,39 +343,92 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
         for (int z = c0; z < c1; ++z) zf[(size_t)z * plane + col] = 7u << ZF_N_SHIFT;
         return;
     }
-    // the column's own reach bounds the window (the gathered range used the global one)
-    int Rc = 0;
-    for (int j = 0; j < cnt; ++j) Rc = max(Rc, (int)(list[j * 256] >> CL_Z_BITS));
-    Rc = cnt ? open_reach(Rc) : 0;
-    int lo = 0, hi = 0;
-    for (int z = c0; z < c1; ++z) {
-        while (hi < cnt && (int)(list[hi * 256] & CL_Z_MASK) <= z + Rc) ++hi;
-        while (lo < hi && (int)(list[lo * 256] & CL_Z_MASK) < z - Rc) ++lo;
-        Front f;
-        front_clear(f);
-        for (int j = lo; j < hi; ++j) {
-            const uint32_t e = list[j * 256];
-            const int dz = z - (int)(e & CL_Z_MASK);
-            const int v = (int)(e >> CL_Z_BITS);
-            const int b = v - dz * dz;
-            if (b > 0) front_insert(f, v, b, dz);
+    // order the list by D, largest first (insertion sort; lists are short)
+    for (int j = 1; j < cnt; ++j) {
+        const uint32_t e = list[j * 256];
+        int q = j - 1;
+        while (q >= 0 && list[q * 256] < e) {            // the key sits in the high bits
+            list[(q + 1) * 256] = list[q * 256];
+            --q;
         }
-        int m = 0;
+        list[(q + 1) * 256] = e;
+    }
+    // slices of the chunk that some listed ball reaches (chunk <= 128: two words)
+    uint64_t cov[2] = {0ull, 0ull};
+    for (int j = 0; j < cnt; ++j) {
+        const uint32_t e = list[j * 256];
+        const int r = open_reach((int)(e >> CL_Z_BITS)), zc = (int)(e & CL_Z_MASK);
+        const int a = max(zc - r, c0) - c0, b = min(zc + r, c1 - 1) - c0;
+        for (int w = 0; w < 2; ++w) {
+            const int lo = max(a, 64 * w), hi = min(b, 64 * w + 63);
+            if (lo <= hi) {
+                const int len = hi - lo + 1;
+                const uint64_t bits = len == 64 ? ~0ull : ((1ull << len) - 1ull);
+                cov[w] |= bits << (lo - 64 * w);
+            }
+        }
+    }
+    for (int z = c0; z < c1; ++z) {
+        const int zr = z - c0;
+        if (!((cov[zr >> 6] >> (zr & 63)) & 1ull)) {         // no listed ball reaches z
+            zf[(size_t)z * plane + col] = 0u;
+            continue;
+        }
+        // Pareto front over (D, residual b = D - dz^2 > 0): scanning by decreasing
+        // D, a group of equal D contributes its largest b when that exceeds every b
+        // of larger D; the scan ends at the first D not above that running maximum
+        // (its residual and all later ones are smaller).  The first ZF_PLANES members
+        // go to the planes; a longer front is written whole to the block's spill
+        // region (second scan).
         uint32_t p[ZF_PLANES];
 #pragma unroll
         for (int k = 0; k < ZF_PLANES; ++k) p[k] = 0u;
+        int m = 0;
+        uint32_t at = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            int maxb = 0, gv = 0, gb = 0, gdz = 0, k = 0;
+            for (int j = 0; j <= cnt; ++j) {
+                int v = 0, dz = 0, bb = 0;
+                if (j < cnt) {
+                    const uint32_t e = list[j * 256];
+                    v = (int)(e >> CL_Z_BITS);
+                    dz = z - (int)(e & CL_Z_MASK);
+                    bb = v - dz * dz;
+                }
+                if (v != gv) {                           // close the group of value gv
+                    if (gb > maxb) {
+                        const uint32_t w = zf_pack(gv, gdz);
+                        if (pass == 0) {
 #pragma unroll
-        for (int k = 0; k < ZF_PLANES; ++k)
-            if (f.v[k] != 0) {
-                const uint32_t w = zf_pack(f.v[k], f.dz[k]);
-#pragma unroll
-                for (int q = 0; q < ZF_PLANES; ++q)
-                    if (q == m) p[q] = w;
-                ++m;
+                            for (int q = 0; q < ZF_PLANES; ++q)
+                                if (q == k) p[q] = w;
+                        } else {
+                            region[at + k] = w;
+                        }
+                        ++k;
+                        maxb = gb;
+                    }
+                    if (v <= maxb) break;                // no residual below v can exceed maxb
+                    gv = v;
+                    gb = 0;
+                }
+                if (bb > gb) {
+                    gb = bb;
+                    gdz = dz;
+                }
             }
+            m = k;
+            if (pass == 1 || m <= ZF_PLANES) break;
+            at = atomicAdd(&s_used, (uint32_t)m);
+            if (at + (uint32_t)m > cap) break;           // region full: rescan instead
+        }
         const size_t i = (size_t)z * plane + col;
-        const uint32_t nfield = f.overflow ? 7u : (uint32_t)m;
-        zf[i] = m ? (p[0] | (nfield << ZF_N_SHIFT)) : 0u;
+        if (m > ZF_PLANES) {
+            zf[i] = at + (uint32_t)m <= cap ? (7u << ZF_N_SHIFT) | ZF_SPILL | ((uint32_t)m << 16) | at
+                                            : 7u << ZF_N_SHIFT;
+            continue;
+        }
+        zf[i] = m ? (p[0] | ((uint32_t)m << ZF_N_SHIFT)) : 0u;
 #pragma unroll
         for (int q = 1; q < ZF_PLANES; ++q)
             if (m > q) zf[q * n + i] = p[q];
@@ -388,6 +518,7 @@ constexpr int REACH_TAB = 4096;
 
 struct TileCtx {
     uint32_t* M;
+    int* disc;             // the wave's disc list in LDS: [4][DL_CAP] (pair end, v, b, x | shift), owner [64]
     const uint8_t* reach;  // LDS table of open_reach
     int H, W;              // tile extent
     int ty0, tx0;          // tile origin (absolute)
@@ -408,46 +539,131 @@ __device__ __forceinline__ void paint_interval(const TileCtx& t, int row, int xs
     atomicMax(base + xe - (1 << k) + 1, v);
 }
 
-// Discs held by the lanes in `mask` (all centred in source row sy, at the lane's
-// column sx) are painted two at a time: lanes 0..31 take one disc, lanes 32..63 the
-// next, and each half sweeps its disc's rows (clipped to the tile) 32 at a time.
-__device__ __forceinline__ void paint_mask(const TileCtx& t, uint64_t mask, int v, int b, int sx,
-                                           int sy, int lane) {
-    const int r = lane & 31;
-    const bool upper = lane >= 32;
-    while (mask) {
-        const int d1 = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
-        int d2 = -1;
-        if (mask) {
-            d2 = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-        }
-        const int v1 = __builtin_amdgcn_readlane(v, d1), b1 = __builtin_amdgcn_readlane(b, d1);
-        const int x1 = __builtin_amdgcn_readlane(sx, d1);
-        int v2 = 0, b2 = 0, x2 = 0;
-        if (d2 >= 0) {
-            v2 = __builtin_amdgcn_readlane(v, d2);
-            b2 = __builtin_amdgcn_readlane(b, d2);
-            x2 = __builtin_amdgcn_readlane(sx, d2);
-        }
-        const bool mine = !upper || d2 >= 0;
-        const int pv = upper ? v2 : v1, pb = upper ? b2 : b1;
-        const int pxr = (upper ? x2 : x1) - t.tx0;          // centre column, tile-relative
-        const int h = mine ? reach_of(t, pb) : 0;
-        const int dlo = max(-h, t.ty0 - sy);
-        const int dhi = mine ? min(h, t.ty0 + t.H - 1 - sy) : dlo - 1;
-        const int rowoff = sy - t.ty0;
-        for (int dyb = dlo; dyb <= dhi; dyb += 32) {
-            const int dy = dyb + r;
-            if (dy <= dhi) {
-                const int hw = reach_of(t, pb - dy * dy);
-                const int xs = max(pxr - hw, 0);
-                const int xe = min(pxr + hw, t.W - 1);
-                if (xs <= xe) paint_interval(t, rowoff + dy, xs, xe, (uint32_t)pv);
-            }
-        }
+constexpr int DL_CAP = 128;          // discs per wave list
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Paint the n discs of the wave's list (all centred in source row sy).  Every
+// (disc, row) pair clipped to the tile is one interval; the pairs are spread over
+// all 64 lanes: each lane sizes two list entries and an inclusive scan over the
+// lanes orders the pairs.  For each window of 64 pairs, the entries whose first
+// pair falls inside it mark that slot in the wave's owner array; a running maximum
+// over the lanes (seeded with the previous window's last owner) then gives each
+// lane the entry its pair belongs to.
+// In 3D the list may hold discs of several source rows of the wave: bits 19..31
+// of an entry's b word hold its source row relative to the tile (+ 4096); in 2D
+// (b up to 2^21) every listed disc is centred in source row sy.
+template <int NDIM>
+__device__ __forceinline__ void disc_unpack(const TileCtx& t, int w, int sy, int& b, int& ro) {
+    if (NDIM == 3) {
+        b = w & (int)ZF_D_MASK;
+        ro = (int)((uint32_t)w >> ZF_D_BITS) - 4096;
+    } else {
+        b = w;
+        ro = sy - t.ty0;
     }
+}
+
+template <int NDIM>
+__device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
+    int* e_end = t.disc;
+    int* e_v = t.disc + DL_CAP;
+    int* e_b = t.disc + 2 * DL_CAP;
+    int* e_x = t.disc + 3 * DL_CAP;
+    int* own = t.disc + 4 * DL_CAP;                 // [64]
+    wave_lds_sync();
+    int cnt[2], dl[2], st[2], local = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int j = 2 * lane + q;
+        cnt[q] = 0;
+        dl[q] = 0;
+        if (j < n) {
+            int b, ro;
+            disc_unpack<NDIM>(t, e_b[j], sy, b, ro);
+            const int h = reach_of(t, b);
+            dl[q] = max(-h, -ro);
+            const int dhi = min(h, t.H - 1 - ro);
+            cnt[q] = max(0, dhi - dl[q] + 1);
+        }
+        local += cnt[q];
+    }
+    int incl = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(incl, (unsigned)off, 64);
+        if (lane >= off) incl += u;
+    }
+    const int total = __shfl(incl, 63, 64);
+    int run = incl - local;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int j = 2 * lane + q;
+        st[q] = run;
+        if (j < n) {
+            e_end[j] = run + cnt[q];
+            // dy of pair i is i + (dlo - first pair index of the disc)
+            e_x[j] = (e_x[j] & 0xfff) | ((dl[q] - run + 16384) << 12);
+        }
+        run += cnt[q];
+    }
+    int carry = 0;
+    for (int base = 0; base < total; base += 64) {
+        own[lane] = -1;
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (cnt[q] > 0 && st[q] >= base && st[q] < base + 64) own[st[q] - base] = 2 * lane + q;
+        wave_lds_sync();
+        int o = own[lane];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(o, (unsigned)off, 64);
+            if (lane >= off) o = max(o, u);
+        }
+        o = max(o, carry);
+        carry = __shfl(o, 63, 64);
+        const int j = base + lane;
+        if (j < total) {
+            const int xw = e_x[o];
+            const int pxr = (xw & 0xfff) - 2048;
+            const int dy = j + (xw >> 12) - 16384;
+            int b, ro;
+            disc_unpack<NDIM>(t, e_b[o], sy, b, ro);
+            const int hw = reach_of(t, b - dy * dy);
+            const int xs = max(pxr - hw, 0);
+            const int xe = min(pxr + hw, t.W - 1);
+            if (xs <= xe) paint_interval(t, ro + dy, xs, xe, (uint32_t)e_v[o]);
+        }
+        wave_lds_sync();
+    }
+}
+
+// Append the discs of the lanes with `has` (value v, squared radius b, centre
+// column sx) to the wave's list (n: wave-uniform length), painting the list first
+// when they would not fit.
+template <int NDIM>
+__device__ __forceinline__ void disc_push(const TileCtx& t, int& n, bool has, int v, int b, int sx, int sy,
+                                          int lane) {
+    const uint64_t m = __ballot(has);
+    if (!m) return;
+    const int k = __popcll(m);
+    if (n + k > DL_CAP) {
+        disc_flush<NDIM>(t, n, sy, lane);
+        n = 0;
+    }
+    if (has) {
+        const int r = n + __popcll(m & ((1ull << lane) - 1ull));
+        t.disc[DL_CAP + r] = v;
+        t.disc[2 * DL_CAP + r] =
+            NDIM == 3 ? (int)((uint32_t)b | ((uint32_t)(sy - t.ty0 + 4096) << ZF_D_BITS)) : b;
+        t.disc[3 * DL_CAP + r] = sx - t.tx0 + 2048;        // 12 bits: |sx - tx0| < 2048
+    }
+    n += k;
 }
 
 template <int NDIM, typename L>
@@ -455,8 +671,10 @@ __global__ void __launch_bounds__(PAINT_THREADS)
 paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             const int32_t* __restrict__ kd, const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
             const uint32_t* __restrict__ toff, uint32_t nlab, int nx, int ny, int nz, int tile_y,
-            uint32_t* __restrict__ counter, int32_t* __restrict__ lt) {
+            uint32_t* __restrict__ counter, int32_t* __restrict__ lt, const uint32_t* __restrict__ spill,
+            int chunk, MeasureSums ms) {
     extern __shared__ uint32_t M[];               // [TILE_LEVELS][tile_y][TILE_STRIDE]
+    __shared__ int s_disc[PAINT_THREADS / 64][4 * DL_CAP + 64];
     __shared__ uint32_t s_item;
     __shared__ uint8_t s_reach[REACH_TAB];
     const int tid = threadIdx.x;
@@ -490,6 +708,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int tt = (int)(item - toff[l]);
         TileCtx t;
         t.M = M;
+        t.disc = s_disc[wid];
         t.reach = s_reach;
         t.ty0 = y0 + (tt / tiles_x) * tile_y;
         t.tx0 = x0 + (tt % tiles_x) * TILE_X;
@@ -499,8 +718,16 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int sy0 = max(y0, t.ty0 - R), sy1 = min(y1, t.ty0 + t.H + R);
         const int sx0 = max(x0, t.tx0 - R), sx1 = min(x1, t.tx0 + t.W + R);
         const int nlev = 32 - __clz(min(t.W, 2 * R + 1));   // levels 0 .. floor(log2(span))
+        // fused measures: this thread's share of the item's volume, radius sums,
+        // largest LT and shell terms (every painted cell is a voxel of label l)
+        uint32_t a_n = 0, a_sn = 0;
+        uint64_t a_q = 0, a_sq = 0;
+        int a_mx = 0;
         for (int pz = (NDIM == 3 ? z0 : 0); pz < (NDIM == 3 ? z1 : 1); ++pz) {
+            int nlist = 0;                                // listed discs (wave-uniform)
+            int sylast = sy0;
             for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
+                sylast = sy;
                 // labels and plane-0 fronts of the whole source row, loaded together
                 constexpr int MAXC = 3;                   // source rows span <= 64 + 2 * 64 columns
                 L lv[MAXC];
@@ -537,23 +764,23 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
 #pragma unroll
                     for (int q = 1; q < ZF_PLANES; ++q) e[q] = 0u;
                     int nent = 0;
-                    bool ovf = false;
+                    bool rescan = false, spilled = false;
                     if (NDIM == 2) {
                         nent = e0 ? 1 : 0;
                     } else if (e0) {
                         const int cc = (int)(e0 >> ZF_N_SHIFT);
-                        ovf = cc == 7;
-                        nent = ovf ? 0 : cc;
+                        spilled = cc == 7 && (e0 & ZF_SPILL);
+                        rescan = cc == 7 && !spilled;
+                        nent = cc == 7 ? 0 : cc;
 #pragma unroll
                         for (int q = 1; q < ZF_PLANES; ++q)
                             if (nent > q) e[q] = zf[q * n + rowi + sx];
                     }
-                    // stored front entries, one disc per lane per pass
+                    // stored front entries
 #pragma unroll
                     for (int p = 0; p < ZF_PLANES; ++p) {
                         const bool has = p < nent;
-                        const uint64_t mask = __ballot(has);
-                        if (!mask) break;
+                        if (!__ballot(has)) break;
                         int v = 0, b = 0;
                         if (has) {
                             if (NDIM == 2) {
@@ -564,13 +791,35 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                                 b = v - dz * dz;
                             }
                         }
-                        paint_mask(t, mask, v, b, sx, sy, lane);
+                        disc_push<NDIM>(t, nlist, has, v, b, sx, sy, lane);
                     }
-                    // fronts larger than the planes: every kept centre of the column
-                    // (within the object's z range) that reaches this slice -- a superset
-                    // of the front.  The wave walks the offsets dz = -R..R together, four
-                    // independent loads at a time, and paints each offset's discs.
-                    if (NDIM == 3 && __ballot(ovf)) {
+                    // long fronts kept in the front pass's spill region
+                    if (NDIM == 3 && __ballot(spilled)) {
+                        int m = 0;
+                        const uint32_t* sp = spill;
+                        if (spilled) {
+                            m = (int)((e0 >> 16) & 0xffu);
+                            const size_t blk = ((size_t)(pz / chunk) * ((ny + 3) / 4) + sy / 4) * ((nx + 63) / 64) +
+                                               sx / 64;
+                            sp = spill + blk * (size_t)(SPILL_PER_SLICE * chunk) + (e0 & 0xffffu);
+                        }
+                        for (int q = 0; __ballot(q < m); ++q) {
+                            const bool has = q < m;
+                            int v = 0, b = 0;
+                            if (has) {
+                                const uint32_t w = sp[q];
+                                v = (int)(w & ZF_D_MASK);
+                                const int dz = (int)((w >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
+                                b = v - dz * dz;
+                            }
+                            disc_push<NDIM>(t, nlist, has, v, b, sx, sy, lane);
+                        }
+                    }
+                    // fronts that did not fit the spill region: every kept centre of the
+                    // column (within the object's z range) that reaches this slice -- a
+                    // superset of the front.  The wave walks the offsets dz = -R..R
+                    // together, four independent loads at a time.
+                    if (NDIM == 3 && __ballot(rescan)) {
                         const size_t col = (size_t)sy * nx + sx;
                         const size_t pl = (size_t)nx * ny;
                         for (int d0 = -R; d0 <= R; d0 += 4) {
@@ -578,20 +827,23 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int zc = pz + d0 + u;
-                                kv[u] = (ovf && d0 + u <= R && zc >= z0 && zc < z1) ? kd[(size_t)zc * pl + col] : 0;
+                                kv[u] = (rescan && d0 + u <= R && zc >= z0 && zc < z1) ? kd[(size_t)zc * pl + col] : 0;
                             }
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int dz = d0 + u;
                                 const int b = kv[u] - dz * dz;
-                                const bool has = kv[u] > 0 && b > 0;
-                                const uint64_t mask = __ballot(has);
-                                if (mask) paint_mask(t, mask, kv[u], b, sx, sy, lane);
+                                disc_push<NDIM>(t, nlist, kv[u] > 0 && b > 0, kv[u], b, sx, sy, lane);
                             }
                         }
                     }
                 }
+                if (NDIM == 2 && nlist) {                 // 2D lists hold one source row
+                    disc_flush<NDIM>(t, nlist, sy, lane);
+                    nlist = 0;
+                }
             }
+            if (nlist) disc_flush<NDIM>(t, nlist, sylast, lane);
             __syncthreads();
             // push-down of the sparse table, one wave per row: level k-1 at column c
             // takes the blocks of level k starting at c and c - 2^(k-1); then write the
@@ -611,13 +863,56 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     }
                 }
                 if (lane < t.W) {
-                    if (val[0]) lt[((size_t)pz * ny + (t.ty0 + row)) * nx + (t.tx0 + lane)] = (int32_t)val[0];
+                    if (val[0]) {
+                        const int gy = t.ty0 + row, gx = t.tx0 + lane;
+                        const size_t gi = ((size_t)pz * ny + gy) * nx + gx;
+                        lt[gi] = (int32_t)val[0];
+                        if (ms.vol) {
+                            const int v = (int)val[0];
+                            const uint64_t q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
+                            const L raw = (L)l;
+                            bool shell = gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1 || lab[gi - 1] != raw ||
+                                         lab[gi + 1] != raw || lab[gi - nx] != raw || lab[gi + nx] != raw;
+                            if (NDIM == 3 && !shell) {
+                                const size_t pl = (size_t)nx * ny;
+                                shell = pz == 0 || pz == nz - 1 || lab[gi - pl] != raw || lab[gi + pl] != raw;
+                            }
+                            ++a_n;
+                            a_q += q;
+                            a_mx = max(a_mx, v);
+                            if (shell) {
+                                ++a_sn;
+                                a_sq += q;
+                            }
+                        }
+                    }
 #pragma unroll
                     for (int k = 0; k < TILE_LEVELS; ++k)
                         if (k < nlev) t.M[k * t.lstride + row * TILE_STRIDE + lane] = 0u;
                 }
             }
             __syncthreads();
+        }
+        if (ms.vol) {                                    // one set of atomics per wave and item
+            uint64_t n1 = a_n, n2 = a_sn, q1 = a_q, q2 = a_sq;
+            int m1 = a_mx;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                n1 += __shfl_xor((unsigned long long)n1, off, 64);
+                n2 += __shfl_xor((unsigned long long)n2, off, 64);
+                q1 += __shfl_xor((unsigned long long)q1, off, 64);
+                q2 += __shfl_xor((unsigned long long)q2, off, 64);
+                m1 = max(m1, __shfl_xor(m1, off, 64));
+            }
+            if (lane == 0 && n1) {
+                atomicAdd((unsigned long long*)&ms.vol[l], (unsigned long long)n1);
+                atomicAdd((unsigned long long*)&ms.sq[l], (unsigned long long)q1);
+                atomicMax(&ms.mx[l], m1);
+                if (n2) {
+                    atomicAdd((unsigned long long*)&ms.shc[l], (unsigned long long)n2);
+                    atomicAdd((unsigned long long*)&ms.ssq[l], (unsigned long long)q2);
+                }
+            }
         }
     }
 }
@@ -627,7 +922,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
 static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct ThickLayout {
-    size_t bb, maxd, toff, counter, zf, kd, total;
+    size_t bb, maxd, toff, counter, zf, kd, spill, total;
 };
 
 static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
@@ -640,6 +935,12 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.counter = at; at += 256;
     o.zf = at;      at += align256((g.ndim == 3 ? ZF_PLANES : 1) * g.n * sizeof(uint32_t));
     o.kd = at;      at += g.ndim == 3 ? align256(g.n * sizeof(int32_t)) : 0;
+    // spill regions of the front pass: one per (64 x 4 column block, z chunk), sized
+    // for the largest chunk (the z extent rounded up by at most 127 slices)
+    o.spill = at;
+    at += g.ndim == 3 ? align256((size_t)((g.nx + 63) / 64) * ((g.ny + 3) / 4) * (g.nz + 127) * SPILL_PER_SLICE *
+                                 sizeof(uint32_t))
+                      : 0;
     o.total = at;
     return o;
 }
@@ -662,15 +963,18 @@ int paint_tile_rows(lt_ctx* ctx) {
         for (const void* f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PAINT_DYN64);
     });
-    // dynamic table + static reach table and work-item word
-    const bool fits64 = ctx->lds_per_block >= dyn64 + REACH_TAB + 64;
+    // dynamic table + static reach table, per-wave disc lists and work-item word
+    const bool fits64 = ctx->lds_per_block >= dyn64 + REACH_TAB + (PAINT_THREADS / 64) * (4 * DL_CAP + 64) * sizeof(int) + 64;
     if (ctx->tune.paint_tile_rows == 32) return 32;
     return fits64 ? 64 : 32;
 }
 
 template <typename L>
 static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* D,
-                                 uint32_t max_label, int32_t* lt, void* scratch, hipStream_t s) {
+                                 uint32_t max_label, int32_t* lt, void* scratch, hipStream_t s,
+                                 const MeasureSums* sums) {
+    const MeasureSums none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    const MeasureSums ms = sums ? *sums : none;
     const ThickLayout lay = thick_layout(g, max_label);
     char* base = (char*)scratch;
     int32_t* bb = (int32_t*)(base + lay.bb);
@@ -679,6 +983,8 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     uint32_t* counter = (uint32_t*)(base + lay.counter);
     uint32_t* zf = (uint32_t*)(base + lay.zf);
     int32_t* kd = (int32_t*)(base + lay.kd);
+    uint32_t* spill = (uint32_t*)(base + lay.spill);
+    const int chunk = ctx->tune.front_chunk > 0 ? ctx->tune.front_chunk : 64;
     uint32_t* gmax = counter + 1;
     const uint32_t nlab = max_label + 1;
 
@@ -690,16 +996,15 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     const dim3 grid((g.nx + 255) / 256, g.ny, g.nz);
     {
         ProfScope _p(ctx, s, "bbox_runs");
-        const int threads = min(1024, ((g.nx + 63) / 64) * 64);
-        bbox_runs<L><<<dim3(1, g.ny, loop_extent(g.nz, g.ny, ctx)), threads, 0, s>>>(
-            lab, g.nx, g.ny, g.nz, max_label, bb, nlab, ctx->d_err);
+        bbox_runs<L><<<dim3(1, (g.ny + BB_ROWS_Y - 1) / BB_ROWS_Y, (g.nz + BB_ROWS_Z - 1) / BB_ROWS_Z), 1024, 0,
+                       s>>>(lab, g.nx, g.ny, g.nz, max_label, bb, nlab, ctx->d_err);
     }
     if (g.ndim == 3) {
         const dim3 b2(64, 4);
         {
             ProfScope _p(ctx, s, "prune3d");
-            const long pb = (long)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
-            prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, loop_extent(g.nz, pb, ctx)), b2, 0, s>>>(
+            prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + PR_TY - 1) / PR_TY, (g.nz + PR_ZB - 1) / PR_ZB),
+                          dim3(64, PR_TY), 0, s>>>(
                 lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd, lt, maxd, ctx->d_err);
         }
         {
@@ -708,9 +1013,8 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         }
         {
             ProfScope _p(ctx, s, "fronts3d");
-            const int chunk = ctx->tune.front_chunk > 0 ? ctx->tune.front_chunk : 64;
             fronts3d<<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + chunk - 1) / chunk), b2, 0, s>>>(
-                kd, g.nx, g.ny, g.nz, chunk, gmax, zf);
+                kd, g.nx, g.ny, g.nz, chunk, gmax, zf, spill);
         }
     } else {
         ProfScope _p(ctx, s, "pixels2d");
@@ -724,28 +1028,31 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     }
     const size_t lds = (size_t)TILE_LEVELS * tile_y * TILE_STRIDE * sizeof(uint32_t);
     // two blocks per CU only when two 32-row tables fit in the LDS
-    const size_t per_block = lds + REACH_TAB + 64;
+    const size_t per_block = lds + REACH_TAB + (PAINT_THREADS / 64) * (4 * DL_CAP + 64) * sizeof(int) + 64;
     const int per_cu = (ctx->tune.paint_blocks_per_cu >= 2 && 2 * per_block <= ctx->lds_per_block) ? 2 : 1;
     const int blocks = ctx->n_cu * per_cu;
     {
         ProfScope _p(ctx, s, "paint_tiles");
         if (g.ndim == 3)
-            paint_tiles<3, L><<<blocks, PAINT_THREADS, lds, s>>>(lab, zf, kd, bb, maxd, toff,
-                                                               nlab, g.nx, g.ny, g.nz, tile_y, counter, lt);
+            paint_tiles<3, L><<<blocks, PAINT_THREADS, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
+                                                               g.nz, tile_y, counter, lt, spill, chunk, ms);
         else
-            paint_tiles<2, L><<<blocks, PAINT_THREADS, lds, s>>>(lab, zf, kd, bb, maxd, toff,
-                                                               nlab, g.nx, g.ny, 1, tile_y, counter, lt);
+            paint_tiles<2, L><<<blocks, PAINT_THREADS, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
+                                                               tile_y, counter, lt, spill, chunk, ms);
     }
     return hip_check(hipGetLastError(), "thickness launch");
 }
 
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           void* scratch, hipStream_t s) {
+                           void* scratch, hipStream_t s, const MeasureSums* sums) {
     switch (dt) {
-        case LT_U16: return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s);
-        case LT_I32: return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s);
-        case LT_U32: return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s);
+        case LT_U16:
+            return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums);
+        case LT_I32:
+            return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums);
+        case LT_U32:
+            return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

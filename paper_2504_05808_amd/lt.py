@@ -66,6 +66,7 @@ def load():
     lib.lt_edt.argtypes = [P, P, I, I, i64p, P, V]
     lib.lt_thickness.argtypes = [P, P, I, I, i64p, P, U32, P, V]
     lib.lt_object_measures.argtypes = [P, P, I, I, i64p, P, U32, ctypes.POINTER(_Measures), V]
+    lib.lt_pipeline.argtypes = [P, P, I, I, i64p, U32, P, P, ctypes.POINTER(_Measures), V]
     lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
     lib.lt_sync_status.argtypes = [P, V]
     lib.lt_ctx_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I)]
@@ -84,7 +85,7 @@ def load():
     lib.lt_status_str.restype = ctypes.c_char_p
     lib.lt_last_error.restype = ctypes.c_char_p
     lib.lt_version.restype = ctypes.c_char_p
-    for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures",
+    for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures", "lt_pipeline",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
               "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
               "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
@@ -277,9 +278,27 @@ def closed_forms(volume, sum_lt_q23, max_lt_sq, shell_count, shell_sum_q23, ndim
     return dict(zip(("mean_lt", "shell_mean_lt", "sphericity", "roundness"), outs))
 
 
+def pipeline(labels: torch.Tensor, max_label: int, hist: bool = False, out=None, ctx: Context | None = None,
+             stream=None):
+    """Whole path in one call (lt_pipeline): (dist_sq, lt_sq, Measures).  `out` may
+    hold preallocated (dist_sq, lt_sq, Measures)."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    if out is None:
+        d = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+        t = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+        m = alloc_measures(int(max_label) + 1, lab.device, hist)
+    else:
+        d, t, m = out
+    ms = _measures_struct(m)
+    _check(ctx._lib.lt_pipeline(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), int(max_label), _ptr(d),
+                                _ptr(t), ctypes.byref(ms), _stream(stream)))
+    return d, t, m
+
+
 def measure(labels: torch.Tensor, max_label: int, hist: bool = False, ctx: Context | None = None,
             stream=None):
-    """Whole pipeline: (dist_sq, lt_sq, Measures)."""
+    """Whole pipeline as three calls: (dist_sq, lt_sq, Measures)."""
     ctx = ctx or default_context()
     d = edt(labels, ctx=ctx, stream=stream)
     t = thickness(labels, d, max_label, ctx=ctx, stream=stream)

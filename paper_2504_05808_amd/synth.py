@@ -380,39 +380,52 @@ def cfg4_volume(i: int, seed: int = 4, n_volumes: int = 64, edges=(96, 384), cou
     return vol, dict(name=f"cfg4[{i}]", objects=objs, n_objects=len(objs))
 
 
-def _cfg5_octant(args):
-    seed, k, n_objects, edge = args
+def _cfg5_block(args):
+    seed, k, n_objects, edge, draws = args
     rng = rng_for(seed * 100003 + k)
     vol = np.zeros((edge, edge, edge), dtype=np.uint16)
-    objs = _place_until(vol, rng, n_objects, ("superellipsoid",))
-    return vol, len(objs)
+    objs = _place_until(vol, rng, n_objects, ("superellipsoid",), max_shapes=draws * n_objects)
+    return k, vol, len(objs)
 
 
 def cfg5_volume(seed: int = 6, edge: int = 1024, n_objects: int = 20000, workers: int | None = None,
-                use_cache: bool = True):
+                use_cache: bool = True, draws: int = 5, progress=None):
     """Evaluation volume of the learned correction: edge^3 uint32 holding ~n_objects
-    objects of the 512^3 distribution.  The volume is built as 8 independent octants
-    (each placed like the 512^3 volume with n_objects / 8 objects, seeded per octant,
-    objects never crossing an octant face), generated in parallel processes; labels
-    are numbered octant by octant."""
-    key = f"cfg5_s{seed}_{edge}_{n_objects}_v1"
+    objects of the 512^3 distribution.  The volume is built as 4 x 4 x 4 independent
+    blocks (each placed like the 512^3 volume with n_objects / 64 objects, seeded per
+    block, objects never crossing a block face; at most draws * n_objects / 64 shapes
+    drawn per block), generated in parallel processes; labels are numbered block by
+    block in block order.  ``progress`` (optional) is called with a line of text as
+    blocks complete."""
+    key = f"cfg5_s{seed}_{edge}_{n_objects}_d{draws}_v2"
     path = _cache_path(key + ".npz") if use_cache else None
     if path and os.path.exists(path):
         with np.load(path) as z:
             return z["vol"], dict(name="cfg5", n_objects=int(z["n"]), cached=True)
-    h = edge // 2
-    jobs = [(seed, k, n_objects // 8, h) for k in range(8)]
-    workers = workers or min(8, os.cpu_count() or 1)
+    nb = 4
+    h = edge // nb
+    jobs = [(seed, k, n_objects // nb ** 3, h, draws) for k in range(nb ** 3)]
+    workers = workers or min(16, os.cpu_count() or 1)
+    parts = {}
+
+    def done(k, v, n):
+        parts[k] = (v, n)
+        if progress and (len(parts) % 8 == 0 or len(parts) == len(jobs)):
+            progress(f"blocks {len(parts)}/{len(jobs)}")
+
     if workers > 1:
         import multiprocessing as mp
         with mp.get_context("spawn").Pool(workers) as pool:
-            parts = pool.map(_cfg5_octant, jobs)
+            for k, v, n in pool.imap_unordered(_cfg5_block, jobs):
+                done(k, v, n)
     else:
-        parts = [_cfg5_octant(j) for j in jobs]
+        for j in jobs:
+            done(*_cfg5_block(j))
     vol = np.zeros((edge, edge, edge), dtype=np.uint32)
     base = 0
-    for k, (v, n) in enumerate(parts):
-        z0, y0, x0 = (k >> 2) * h, ((k >> 1) & 1) * h, (k & 1) * h
+    for k in range(nb ** 3):
+        v, n = parts[k]
+        z0, y0, x0 = (k // (nb * nb)) * h, ((k // nb) % nb) * h, (k % nb) * h
         sub = v.astype(np.uint32)
         sub[sub != 0] += base
         vol[z0:z0 + h, y0:y0 + h, x0:x0 + h] = sub

@@ -40,6 +40,7 @@ def test_null_context_rejected():
     assert lib.lt_edt(None, ctypes.c_void_p(8), lt.LT_U16, 3, shape, ctypes.c_void_p(8), None) == 1
     assert lib.lt_thickness(None, None, lt.LT_U16, 3, shape, None, 5, None, None) == 1
     assert lib.lt_sync_status(None, None) == 1
+    assert lib.lt_pipeline(None, ctypes.c_void_p(8), lt.LT_U16, 3, shape, 5, None, None, None, None) == 1
     assert b"ctx" in lib.lt_last_error()
 
 

@@ -158,7 +158,10 @@ def test_adamw_first_step_closed_form(gpu):
         is_bias[o:o + n] = True
     decay = np.where(is_bias, 0.0, lr * wd)
     expect = w0 - decay * w0 - lr * g / (np.abs(g) + 1e-8)
-    np.testing.assert_allclose(w1, expect, rtol=0, atol=2e-7 + 1e-6 * np.abs(w0))
+    err = np.abs(w1 - expect)
+    bad = np.nonzero(err > 2e-7 + 1e-6 * np.abs(w0))[0]
+    block = {i: next(k for k, (o, n) in R.OFF.items() if o <= i < o + n) for i in bad[:8]}
+    assert len(bad) == 0, (len(bad), [(int(i), block[i], w0[i], g[i], w1[i], expect[i]) for i in bad[:8]])
     m, v = net.moments()
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-6, atol=0)
     np.testing.assert_allclose(v, 0.001 * g * g, rtol=5e-5, atol=0)     # 1 - 0.999f = 0.001 (1 - 1.3e-5)
@@ -315,3 +318,44 @@ def test_learned_correction_beats_closed_form(gpu):
     # recalibration of the closed form fitted on the same training objects
     assert e_net < 0.3 * e_cf
     assert e_net < 0.95 * e_aff
+
+
+EVAL_TARGETS = os.path.join(ROOT, "tests", "golden", "cfg5_targets.npz")
+
+
+def test_learned_correction_on_1024_volume(gpu):
+    """The evaluation volume (1024^3 uint32, objects of the 512^3 distribution): the
+    whole GPU path measures every object, the network trained on the oracle-made
+    set corrects the closed form, and the corrected sphericity is closer to the mesh
+    sphericity (stored by a script that calls only the oracles) than the closed
+    form."""
+    torch, lt = gpu
+    if not os.path.exists(EVAL_TARGETS):
+        pytest.skip("evaluation targets not generated")
+    tg = np.load(EVAL_TARGETS)
+    x, s_lt, s_mesh, _ = _dataset()
+    net = fit_correction(torch, lt, x, s_lt, s_mesh)
+    _note("network trained; generating the 1024^3 volume")
+    vol, meta = synth.cfg5_volume(draws=int(tg["draws"]), workers=16, progress=_note)
+    assert synth.digest(vol) == str(tg["digest"]) and meta["n_objects"] == int(tg["n_objects"])
+    ml = int(meta["n_objects"])
+    _note(f"volume ready: {ml} objects; running the path")
+    t = torch.from_numpy(vol).cuda()
+    del vol
+    _, _, m = lt.measure(t, ml, hist=True)
+    feats = lt.mlp_features(m)
+    s_corr, nf = net.correct(feats, m.sphericity)
+    lt.default_context().sync_status()
+    labels = tg["labels"]
+    sc = s_corr.cpu().double().numpy()[labels]
+    sl = m.sphericity.cpu().double().numpy()[labels]
+    ref = tg["s_mesh"]
+    coef = np.polyfit(s_lt, s_mesh, 1)                    # affine recalibration on the training set
+    e_cf = np.abs(sl - ref).mean()
+    e_aff = np.abs(np.polyval(coef, sl) - ref).mean()
+    e_net = np.abs(sc - ref).mean()
+    n_fb = int(nf.cpu()[0]) - (ml + 1 - len(labels))          # absent labels always fall back
+    _note(f"1024^3: {len(labels)} objects, MAE closed form {e_cf:.4f}, affine {e_aff:.4f}, "
+          f"corrected {e_net:.4f}, fallbacks {n_fb}")
+    assert n_fb <= 0.02 * len(labels)
+    assert e_net < 0.5 * e_cf

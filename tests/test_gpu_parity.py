@@ -1,4 +1,5 @@
-"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, in both
+forms (lt_edt + lt_thickness + lt_object_measures, and the fused lt_pipeline).
 
 Distances and local thickness are compared bit-exactly (integers); per-object
 volume, shell count and max LT exactly; the FP32 measures within 1e-5 relative
@@ -35,11 +36,19 @@ def _note(msg):
     sys.stdout.flush()
 
 
-def run_gpu(gpu, lab, max_label=None, hist=False):
+def run_gpu(gpu, lab, max_label=None, hist=False, fused=None):
+    """The path through the C ABI.  fused=None runs both forms (three calls and the
+    one-call lt_pipeline), checks that they agree bit for bit and returns one."""
+    if fused is None:
+        a = run_gpu(gpu, lab, max_label, hist, fused=False)
+        b = run_gpu(gpu, lab, max_label, hist, fused=True)
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"fused vs separate: {k}")
+        return a
     torch, lt = gpu
     max_label = int(lab.max()) if max_label is None else max_label
     t = torch.from_numpy(np.ascontiguousarray(lab)).cuda()
-    d, ltsq, m = lt.measure(t, max_label, hist=hist)
+    d, ltsq, m = (lt.pipeline if fused else lt.measure)(t, max_label, hist=hist)
     lt.default_context().sync_status()
     out = dict(dist_sq=d.cpu().numpy().astype(np.int64), lt_sq=ltsq.cpu().numpy().astype(np.int64))
     for k in ("volume", "shell_count", "max_lt_sq"):
