@@ -40,7 +40,7 @@ def kernel_bytes(name: str, n: int, f: float, label_bytes: int = 2) -> float | N
         "bbox_runs": lb * n,                        # labels
         "prune3d": 4 * n + lb * f * n + 4 * n + 4 * (1 - f) * n,   # D, object labels -> kept field; LT = 0 outside
         "fronts3d": 4 * n + 16 * f * n,             # kept field -> 4 front planes of object voxels
-        "paint_tiles": (lb + 16 + 4) * f * n,       # labels + fronts of object voxels -> LT
+        "paint_tiles": (lb + 16 + 4 + 4) * f * n,   # labels, fronts, D (shell test) of object voxels -> LT
         "object_sums": (lb + 4) * n,                # labels + LT
     }
     return table.get(name)
@@ -336,6 +336,11 @@ def main():
                     help="measure the batched graph form against per-volume launches instead")
     ap.add_argument("--batch-volumes", type=int, default=64)
     ap.add_argument("--mlp", action="store_true", help="measure the learned correction instead")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner choose the kernel knobs first (outside the timed region)")
+    ap.add_argument("--paint-rows", type=int, default=0, help="paint tile rows (32 or 64; 0 = default)")
+    ap.add_argument("--paint-per-cu", type=int, default=0, help="paint blocks per CU (1 or 2; 0 = default)")
+    ap.add_argument("--front-chunk", type=int, default=0, help="z-front chunk (32, 64, 128; 0 = default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for the HBM counters)")
     args = ap.parse_args()
@@ -371,7 +376,15 @@ def main():
     t = torch.empty(vol.shape, dtype=torch.int32, device=dev)
     m = lt.alloc_measures(max_label + 1, dev)
 
-    print(f"# device {ctx.info()}", flush=True)
+    knobs = {k: v for k, v in (("paint_tile_rows", args.paint_rows), ("paint_blocks_per_cu", args.paint_per_cu),
+                               ("front_chunk", args.front_chunk)) if v}
+    if knobs:
+        ctx.set_tuning(**knobs)
+    if args.autotune:
+        t_at = time.perf_counter()
+        ctx.autotune(lab, max_label, cache_path=os.environ.get("LT_AUTOTUNE_CACHE"), repeats=2)
+        print(f"# autotune {time.perf_counter() - t_at:.1f}s -> {ctx.get_tuning()}", flush=True)
+    print(f"# device {ctx.info()} tuning {ctx.get_tuning()}", flush=True)
     if args.copy_calibration:
         copy_calibration(dev)
 
@@ -464,6 +477,7 @@ def main():
                          "note": "36 B/voxel pass-structured algorithmic traffic / step time"},
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "device": ctx.info(),
+        "tuning": ctx.get_tuning(),
         "kernel_ms": {k: round(v["avg_ms"], 4) for k, v in kernels.items()},
         "kernel_GBs": {k: round(v["GBs"], 1) for k, v in kernels.items() if "GBs" in v},
         "ball_cover": None if work is None else {"work_points": work, "kept_centres": kept,

@@ -148,27 +148,22 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
                 wl[u] = s_val[(r - k - u) * 64 + tx];
                 wh[u] = s_val[(r + k + u) * 64 + tx];
             }
+            // branch-free steps: a step is active while k^2 < best (tested once per
+            // step, as in the plain loop); a boundary bit ends that direction with
+            // candidate k^2, any other position offers k^2 + its value
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int kk = (k + u) * (k + u);
-                if (kk < best) {
-                    if (dlo) {
-                        if (wl[u] & LINE_BLK_DN) {               // label(p-k) != label(p-k+1)
-                            best = min(best, kk);
-                            dlo = false;
-                        } else {
-                            best = min(best, kk + (int)(wl[u] & LINE_VAL));
-                        }
-                    }
-                    if (dhi) {
-                        if (wh[u] & LINE_BLK_UP) {               // label(p+k) != label(p+k-1)
-                            best = min(best, kk);
-                            dhi = false;
-                        } else {
-                            best = min(best, kk + (int)(wh[u] & LINE_VAL));
-                        }
-                    }
-                }
+                const bool act = kk < best;
+                const bool lb = (wl[u] & LINE_BLK_DN) != 0u;   // label(p-k) != label(p-k+1)
+                const bool hb = (wh[u] & LINE_BLK_UP) != 0u;   // label(p+k) != label(p+k-1)
+                const int cl = lb ? kk : kk + (int)(wl[u] & LINE_VAL);
+                const int ch = hb ? kk : kk + (int)(wh[u] & LINE_VAL);
+                const bool ul = act && dlo, uh = act && dhi;
+                best = ul ? min(best, cl) : best;
+                best = uh ? min(best, ch) : best;
+                dlo = dlo && !(ul && lb);
+                dhi = dhi && !(uh && hb);
             }
             k += 4;
         }

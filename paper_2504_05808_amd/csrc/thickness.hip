@@ -34,8 +34,10 @@ namespace lt {
 
 // ------------------------------------------------------------------ small kernels
 
-__global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uint32_t* gmax) {
+__global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uint32_t* gmax, int32_t* colmax,
+                                  size_t ncol) {
     const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t c = l; c < ncol; c += (size_t)gridDim.x * blockDim.x) colmax[c] = 0;
     if (l == 0) *gmax = 0u;
     if (l >= nlab) return;
     for (int k = 0; k < 3; ++k) {
@@ -168,20 +170,6 @@ __device__ __forceinline__ void wave_label_max(uint32_t l, bool valid, int d, in
     }
 }
 
-// Largest per-label maximum (the global reach used by the front pass); one block.
-__global__ void __launch_bounds__(1024)
-max_over_labels(const int32_t* __restrict__ maxd, uint32_t nlab, uint32_t* __restrict__ gmax) {
-    __shared__ int s[1024];
-    int m = 0;
-    for (uint32_t l = threadIdx.x; l < nlab; l += 1024) m = max(m, maxd[l]);
-    s[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 512; off >= 1; off >>= 1) {
-        if ((int)threadIdx.x < off) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *gmax = (uint32_t)s[0];
-}
 
 // One thread per voxel: background LT = 0; a centre is kept unless a 26-neighbour's
 // open ball contains its ball; kd = D for kept centres, 0 elsewhere; per-label max
@@ -192,7 +180,7 @@ template <typename L>
 __global__ void __launch_bounds__(512)
 prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny, int nz,
         uint32_t max_label, const int32_t* __restrict__ tab, int32_t* __restrict__ kd,
-        int32_t* __restrict__ lt, int32_t* __restrict__ maxd, uint32_t* err) {
+        int32_t* __restrict__ lt, int32_t* __restrict__ maxd, int32_t* __restrict__ colmax, uint32_t* err) {
     // a block walks PR_ZB consecutive slices of a 64 x PR_TY tile; D of the slices
     // below, at and above the current one (tile + 1 voxel halo) rotate through LDS
     __shared__ int32_t s_d[3][PR_H][PR_W];
@@ -236,6 +224,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     fetch(zs);
     store(zs);
     fetch(zs + 1);
+    int cmax = 0;                                        // largest kept D of this column's slices
     for (int z = zs; z < ze; ++z) {
         store(z + 1);
         __syncthreads();
@@ -272,6 +261,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
             kd[i] = keep ? d : 0;
             if (d <= 0) lt[i] = 0;
         }
+        if (keep) cmax = max(cmax, d);
         // per-label largest kept D: wave maxima merged in the block table
         uint64_t active = __ballot(keep);
         while (active) {
@@ -291,6 +281,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         __syncthreads();                                 // the slot of z - 1 is reloaded next
     }
     if (tid < PR_TAB && s_key[tid] != 0u) atomicMax(&maxd[s_key[tid]], s_max[tid]);
+    if (cmax > 0) atomicMax(&colmax[(size_t)y * nx + x], cmax);
 }
 
 // ------------------------------------------------------------------ 3D z-fronts
@@ -298,7 +289,8 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
 constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
 
 // One thread per (column, chunk of `chunk` slices).  The kept centres of the
-// column within the chunk grown by the global reach R are gathered (batched loads)
+// column within the chunk grown by the column's reach R (of its largest kept D) are
+// gathered (batched loads)
 // into the thread's LDS list and ordered by D; then for each slice of the chunk
 // one scan of that list yields the Pareto front over (value D, residual
 // D - dz^2 > 0), stored in the front planes or, when longer than the planes, in
@@ -307,7 +299,7 @@ constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
 // column instead (same result).
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
-         const uint32_t* __restrict__ gmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
+         const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
     __shared__ uint32_t s_list[256 * FR_CAP];
     __shared__ uint32_t s_used;                    // words of the block's spill region in use
     const int tid = threadIdx.y * 64 + threadIdx.x;
@@ -320,10 +312,15 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     const uint32_t cap = (uint32_t)(SPILL_PER_SLICE * chunk);
     uint32_t* region = spill + ((size_t)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * cap;
     const int c0 = blockIdx.z * chunk, c1 = min(nz, c0 + chunk);
-    const int R = open_reach(max((int)*gmax, 1));
-    const int zlo = max(0, c0 - R), zhi = min(nz, c1 + R);
     const size_t plane = (size_t)ny * nx;
     const size_t col = (size_t)y * nx + x;
+    const int cm = colmax[col];
+    if (cm == 0) {                                       // no kept centre in the column
+        for (int z = c0; z < c1; ++z) zf[(size_t)z * plane + col] = 0u;
+        return;
+    }
+    const int R = open_reach(cm);                        // no ball of the column reaches farther
+    const int zlo = max(0, c0 - R), zhi = min(nz, c1 + R);
     const size_t n = plane * nz;
     int cnt = 0;
     bool full = false;
@@ -672,9 +669,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             const int32_t* __restrict__ kd, const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
             const uint32_t* __restrict__ toff, uint32_t nlab, int nx, int ny, int nz, int tile_y,
             uint32_t* __restrict__ counter, int32_t* __restrict__ lt, const uint32_t* __restrict__ spill,
-            int chunk, MeasureSums ms) {
-    extern __shared__ uint32_t M[];               // [TILE_LEVELS][tile_y][TILE_STRIDE]
-    __shared__ int s_disc[PAINT_THREADS / 64][4 * DL_CAP + 64];
+            int chunk, MeasureSums ms, const int32_t* __restrict__ Dmap) {
+    // dynamic LDS: the sparse table [TILE_LEVELS][tile_y][TILE_STRIDE], then one disc
+    // list per wave
+    extern __shared__ uint32_t M[];
     __shared__ uint32_t s_item;
     __shared__ uint8_t s_reach[REACH_TAB];
     const int tid = threadIdx.x;
@@ -708,7 +706,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int tt = (int)(item - toff[l]);
         TileCtx t;
         t.M = M;
-        t.disc = s_disc[wid];
+        t.disc = (int*)(M + TILE_LEVELS * tile_y * TILE_STRIDE) + wid * (4 * DL_CAP + 64);
         t.reach = s_reach;
         t.ty0 = y0 + (tt / tiles_x) * tile_y;
         t.tx0 = x0 + (tt % tiles_x) * TILE_X;
@@ -726,20 +724,33 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         for (int pz = (NDIM == 3 ? z0 : 0); pz < (NDIM == 3 ? z1 : 1); ++pz) {
             int nlist = 0;                                // listed discs (wave-uniform)
             int sylast = sy0;
-            for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
-                sylast = sy;
-                // labels and plane-0 fronts of the whole source row, loaded together
-                constexpr int MAXC = 3;                   // source rows span <= 64 + 2 * 64 columns
-                L lv[MAXC];
-                uint32_t ev[MAXC];
-                const size_t rowi = ((size_t)pz * ny + sy) * nx;
+            // labels and plane-0 fronts of a whole source row, loaded together; the
+            // next row of the wave is fetched while the current one is processed
+            constexpr int MAXC = 3;                       // source rows span <= 64 + 2 * 64 columns
+            L nlv[MAXC];
+            uint32_t nev[MAXC];
+            auto fetch_row = [&](int syn) {
+                const size_t ri = ((size_t)pz * ny + syn) * nx;
 #pragma unroll
                 for (int c = 0; c < MAXC; ++c) {
                     const int sx = sx0 + c * 64 + lane;
-                    const bool in = sx < sx1;
-                    lv[c] = in ? lab[rowi + sx] : L(0);
-                    ev[c] = in ? zf[rowi + sx] : 0u;
+                    const bool in = syn < sy1 && sx < sx1;
+                    nlv[c] = in ? lab[ri + sx] : L(0);
+                    nev[c] = in ? zf[ri + sx] : 0u;
                 }
+            };
+            fetch_row(sy0 + wid);
+            for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
+                sylast = sy;
+                L lv[MAXC];
+                uint32_t ev[MAXC];
+#pragma unroll
+                for (int c = 0; c < MAXC; ++c) {
+                    lv[c] = nlv[c];
+                    ev[c] = nev[c];
+                }
+                fetch_row(sy + nwaves);
+                const size_t rowi = ((size_t)pz * ny + sy) * nx;
                 for (int c = 0; c * 64 < sx1 - sx0; ++c) {
                     const int sx = sx0 + c * 64 + lane;
                     L lc;
@@ -870,13 +881,9 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                         if (ms.vol) {
                             const int v = (int)val[0];
                             const uint64_t q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
-                            const L raw = (L)l;
-                            bool shell = gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1 || lab[gi - 1] != raw ||
-                                         lab[gi + 1] != raw || lab[gi - nx] != raw || lab[gi + nx] != raw;
-                            if (NDIM == 3 && !shell) {
-                                const size_t pl = (size_t)nx * ny;
-                                shell = pz == 0 || pz == nz - 1 || lab[gi - pl] != raw || lab[gi + pl] != raw;
-                            }
+                            // on the shell exactly when a face neighbour (or the image
+                            // border) is not of the object: D = 1
+                            const bool shell = Dmap[gi] == 1;
                             ++a_n;
                             a_q += q;
                             a_mx = max(a_mx, v);
@@ -922,7 +929,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
 static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct ThickLayout {
-    size_t bb, maxd, toff, counter, zf, kd, spill, total;
+    size_t bb, maxd, toff, counter, zf, kd, spill, colmax, total;
 };
 
 static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
@@ -941,6 +948,7 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     at += g.ndim == 3 ? align256((size_t)((g.nx + 63) / 64) * ((g.ny + 3) / 4) * (g.nz + 127) * SPILL_PER_SLICE *
                                  sizeof(uint32_t))
                       : 0;
+    o.colmax = at;  at += g.ndim == 3 ? align256((size_t)g.ny * g.nx * sizeof(int32_t)) : 0;
     o.total = at;
     return o;
 }
@@ -949,9 +957,17 @@ size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label) {
     return thick_layout(g, max_label).total;
 }
 
-// Tile rows of the paint pass: 64 when the device lets one block hold the 64-row
-// table (7 levels x 64 x 65 words = 116,480 B), else 32.
-constexpr size_t PAINT_DYN64 = (size_t)TILE_LEVELS * 64 * TILE_STRIDE * sizeof(uint32_t);
+// Dynamic LDS of a paint block: the sparse table for `rows` tile rows plus one disc
+// list per wave.
+static size_t paint_lds(int rows, int threads) {
+    return (size_t)TILE_LEVELS * rows * TILE_STRIDE * sizeof(uint32_t) +
+           (size_t)(threads / 64) * (4 * DL_CAP + 64) * sizeof(int);
+}
+
+// Tile rows of the paint pass: 64 when the device lets one 1024-thread block hold
+// the 64-row table (7 levels x 64 x 65 words = 116,480 B) and its wave lists, else 32.
+constexpr size_t PAINT_DYN64 = (size_t)TILE_LEVELS * 64 * TILE_STRIDE * sizeof(uint32_t) +
+                               (size_t)(PAINT_THREADS / 64) * (4 * DL_CAP + 64) * sizeof(int);
 
 int paint_tile_rows(lt_ctx* ctx) {
     const size_t dyn64 = PAINT_DYN64;
@@ -963,8 +979,8 @@ int paint_tile_rows(lt_ctx* ctx) {
         for (const void* f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PAINT_DYN64);
     });
-    // dynamic table + static reach table, per-wave disc lists and work-item word
-    const bool fits64 = ctx->lds_per_block >= dyn64 + REACH_TAB + (PAINT_THREADS / 64) * (4 * DL_CAP + 64) * sizeof(int) + 64;
+    // dynamic table and wave lists + static reach table and work-item word
+    const bool fits64 = ctx->lds_per_block >= dyn64 + REACH_TAB + 64;
     if (ctx->tune.paint_tile_rows == 32) return 32;
     return fits64 ? 64 : 32;
 }
@@ -984,13 +1000,16 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     uint32_t* zf = (uint32_t*)(base + lay.zf);
     int32_t* kd = (int32_t*)(base + lay.kd);
     uint32_t* spill = (uint32_t*)(base + lay.spill);
+    int32_t* colmax = (int32_t*)(base + lay.colmax);
+    const size_t ncol = g.ndim == 3 ? (size_t)g.ny * g.nx : 0;
     const int chunk = ctx->tune.front_chunk > 0 ? ctx->tune.front_chunk : 64;
     uint32_t* gmax = counter + 1;
     const uint32_t nlab = max_label + 1;
 
     {
         ProfScope _p(ctx, s, "init_label_arrays");
-        init_label_arrays<<<(nlab + 255) / 256, 256, 0, s>>>(bb, maxd, nlab, gmax);
+        const size_t work = std::max((size_t)nlab, std::min(ncol, (size_t)1 << 20));
+        init_label_arrays<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(bb, maxd, nlab, gmax, colmax, ncol);
     }
     const dim3 block(256);
     const dim3 grid((g.nx + 255) / 256, g.ny, g.nz);
@@ -1005,16 +1024,12 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             ProfScope _p(ctx, s, "prune3d");
             prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + PR_TY - 1) / PR_TY, (g.nz + PR_ZB - 1) / PR_ZB),
                           dim3(64, PR_TY), 0, s>>>(
-                lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd, lt, maxd, ctx->d_err);
-        }
-        {
-            ProfScope _p(ctx, s, "max_over_labels");
-            max_over_labels<<<1, 1024, 0, s>>>(maxd, nlab, gmax);
+                lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd, lt, maxd, colmax, ctx->d_err);
         }
         {
             ProfScope _p(ctx, s, "fronts3d");
             fronts3d<<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + chunk - 1) / chunk), b2, 0, s>>>(
-                kd, g.nx, g.ny, g.nz, chunk, gmax, zf, spill);
+                kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill);
         }
     } else {
         ProfScope _p(ctx, s, "pixels2d");
@@ -1026,19 +1041,21 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         ProfScope _p(ctx, s, "plan_tiles");
         plan_tiles<<<1, 1024, 0, s>>>(bb, nlab, tile_y, toff, counter);
     }
-    const size_t lds = (size_t)TILE_LEVELS * tile_y * TILE_STRIDE * sizeof(uint32_t);
-    // two blocks per CU only when two 32-row tables fit in the LDS
-    const size_t per_block = lds + REACH_TAB + (PAINT_THREADS / 64) * (4 * DL_CAP + 64) * sizeof(int) + 64;
-    const int per_cu = (ctx->tune.paint_blocks_per_cu >= 2 && 2 * per_block <= ctx->lds_per_block) ? 2 : 1;
-    const int blocks = ctx->n_cu * per_cu;
+    // two blocks of 512 threads per CU (32-row tiles) when both fit in the LDS, else one
+    // block of 1024 threads: two blocks overlap each other's slice barriers
+    const bool two = ctx->tune.paint_blocks_per_cu >= 2 &&
+                     2 * (paint_lds(tile_y, PAINT_THREADS / 2) + REACH_TAB + 64) <= ctx->lds_per_block;
+    const int threads = two ? PAINT_THREADS / 2 : PAINT_THREADS;
+    const size_t lds = paint_lds(tile_y, threads);
+    const int blocks = ctx->n_cu * (two ? 2 : 1);
     {
         ProfScope _p(ctx, s, "paint_tiles");
         if (g.ndim == 3)
-            paint_tiles<3, L><<<blocks, PAINT_THREADS, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
-                                                               g.nz, tile_y, counter, lt, spill, chunk, ms);
+            paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
+                                                               g.nz, tile_y, counter, lt, spill, chunk, ms, D);
         else
-            paint_tiles<2, L><<<blocks, PAINT_THREADS, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
-                                                               tile_y, counter, lt, spill, chunk, ms);
+            paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
+                                                               tile_y, counter, lt, spill, chunk, ms, D);
     }
     return hip_check(hipGetLastError(), "thickness launch");
 }

@@ -245,3 +245,15 @@ def test_measure_values_on_mixed_labels_are_per_object():
         assert both[k][1] == alone[k][1]
     for k in ("sum_lt", "shell_sum_lt", "sphericity", "roundness"):
         assert both[k][1] == pytest.approx(alone[k][1], rel=1e-12)
+
+
+def test_shell_is_distance_one():
+    """The shell (an object voxel with a face neighbour of another label or outside
+    the image) is exactly the set of object voxels at squared distance 1 from the
+    nearest non-object position -- the identity the fused measures use."""
+    for seed, shape in [(1, (17, 23)), (2, (9, 14, 11)), (3, (1, 30, 7)), (4, (12, 1, 1))]:
+        rng = synth.rng_for(3000 + seed)
+        for blob in (1, 3):
+            lab = synth.random_labels(rng, shape, n_labels=4, p_bg=0.2, blob=blob)
+            D = O.edt_sq(lab)
+            np.testing.assert_array_equal(O.shell_mask(lab), (lab != 0) & (D == 1))
