@@ -28,7 +28,7 @@ constexpr int TILE_STRIDE = TILE_X + 1;
 constexpr int TILE_LEVELS = 7;                 // interval lengths 1..64 -> levels 0..6
 constexpr int PAINT_THREADS = 1024;
 
-// Row scans (EDT pass x, bounding boxes): rows up to 2048 voxels = 32 wave chunks.
+// Row scans (EDT pass x): rows up to 2048 voxels = 32 wave chunks.
 constexpr int ROW_MAX_CHUNKS = 32;
 
 // Packed z-front entry (3D): bits 0..18 D of the centre, 19..28 dz + 512 (dz is
@@ -43,9 +43,9 @@ constexpr uint32_t ZF_DZ_MASK = 1023u;
 constexpr uint32_t ZF_N_SHIFT = 29;
 constexpr int ZF_PLANES = 4;
 constexpr uint32_t ZF_SPILL = 1u << 28;
-// Spill words per (64 x 4 column block, slice) of the front pass: a quarter word per
+// Spill words per (64 x 4 column block, slice) of the front pass: half a word per
 // voxel; a block whose long fronts need more falls back to rescans.
-constexpr int SPILL_PER_SLICE = 64;
+constexpr int SPILL_PER_SLICE = 128;
 
 // Column-list entry (3D): (D << 11) | z.
 constexpr uint32_t CL_Z_BITS = 11;

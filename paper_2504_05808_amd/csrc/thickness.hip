@@ -294,9 +294,9 @@ constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
 // into the thread's LDS list and ordered by D; then for each slice of the chunk
 // one scan of that list yields the Pareto front over (value D, residual
 // D - dz^2 > 0), stored in the front planes or, when longer than the planes, in
-// the block's spill region.  A list that would exceed FR_CAP marks the chunk's
-// fronts as "rescan" (count 7); the paint pass then takes every centre of the
-// column instead (same result).
+// the block's spill region.  A list that would exceed FR_CAP, or a spill region
+// that is full, marks the fronts "rescan" (count 7 without ZF_SPILL); the paint
+// pass then takes every centre of the column instead (same result).
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
@@ -520,6 +520,7 @@ struct TileCtx {
     int H, W;              // tile extent
     int ty0, tx0;          // tile origin (absolute)
     int lstride;           // words per level = H * TILE_STRIDE
+    unsigned long long* dirty;   // LDS mask of the tile rows painted in the current slice
 };
 
 __device__ __forceinline__ int reach_of(const TileCtx& t, int w) {
@@ -596,6 +597,23 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
         if (lane >= off) incl += u;
     }
     const int total = __shfl(incl, 63, 64);
+    {                                               // rows these discs paint
+        unsigned long long rows = 0ull;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int j = 2 * lane + q;
+            if (j < n && cnt[q] > 0) {
+                int b, ro;
+                disc_unpack<NDIM>(t, e_b[j], sy, b, ro);
+                const int r0 = ro + dl[q];
+                const unsigned long long span = cnt[q] >= 64 ? ~0ull : ((1ull << cnt[q]) - 1ull);
+                rows |= span << r0;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rows |= __shfl_xor(rows, off, 64);
+        if (lane == 0 && rows) atomicOr(t.dirty, rows);
+    }
     int run = incl - local;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -674,6 +692,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     // list per wave
     extern __shared__ uint32_t M[];
     __shared__ uint32_t s_item;
+    __shared__ unsigned long long s_dirty[2];      // painted rows, by slice parity
     __shared__ uint8_t s_reach[REACH_TAB];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
@@ -685,7 +704,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     for (int q = tid; q < TILE_LEVELS * tile_y * TILE_STRIDE; q += blockDim.x) M[q] = 0u;
     for (int w = tid; w < REACH_TAB; w += blockDim.x) s_reach[w] = (uint8_t)(w > 0 ? open_reach(w) : 0);
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(counter, 1u);
+        if (tid == 0) {
+            s_item = atomicAdd(counter, 1u);
+            s_dirty[0] = s_dirty[1] = 0ull;
+        }
         __syncthreads();
         const uint32_t item = s_item;
         __syncthreads();
@@ -722,6 +744,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         uint64_t a_q = 0, a_sq = 0;
         int a_mx = 0;
         for (int pz = (NDIM == 3 ? z0 : 0); pz < (NDIM == 3 ? z1 : 1); ++pz) {
+            t.dirty = &s_dirty[pz & 1];
             int nlist = 0;                                // listed discs (wave-uniform)
             int sylast = sy0;
             // labels and plane-0 fronts of a whole source row, loaded together; the
@@ -856,10 +879,14 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             }
             if (nlist) disc_flush<NDIM>(t, nlist, sylast, lane);
             __syncthreads();
-            // push-down of the sparse table, one wave per row: level k-1 at column c
-            // takes the blocks of level k starting at c and c - 2^(k-1); then write the
-            // painted cells and clear every level of the row
+            // push-down of the sparse table, one wave per painted row: level k-1 at
+            // column c takes the blocks of level k starting at c and c - 2^(k-1); then
+            // write the painted cells and clear every level of the row.  Rows no disc
+            // reached are still clear and hold no voxel of the object.
+            const unsigned long long painted = *t.dirty;
+            if (tid == 0) s_dirty[(pz + 1) & 1] = 0ull;   // the next slice's mask
             for (int row = wid; row < t.H; row += nwaves) {
+                if (!((painted >> row) & 1ull)) continue;
                 uint32_t val[TILE_LEVELS];
 #pragma unroll
                 for (int k = 0; k < TILE_LEVELS; ++k)
