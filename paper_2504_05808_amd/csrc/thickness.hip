@@ -537,6 +537,30 @@ __device__ __forceinline__ void paint_interval(const TileCtx& t, int row, int xs
     atomicMax(base + xe - (1 << k) + 1, v);
 }
 
+// Inclusive scans over the 64 lanes of a wave with DPP moves (VALU only, no LDS
+// traffic): row_shr by 1, 2, 4, 8 within each row of 16 lanes, then row_bcast:15
+// (rows 1 and 3 take the last lane of the row before) and row_bcast:31 (rows 2 and 3
+// take lane 31).  Lanes without a source take the identity.
+__device__ __forceinline__ int wave_scan_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ int wave_scan_max(int x) {                // identity -1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 constexpr int DL_CAP = 128;          // discs per wave list
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -590,12 +614,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
         }
         local += cnt[q];
     }
-    int incl = local;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(incl, (unsigned)off, 64);
-        if (lane >= off) incl += u;
-    }
+    const int incl = wave_scan_add(local);
     const int total = __shfl(incl, 63, 64);
     {                                               // rows these discs paint
         unsigned long long rows = 0ull;
@@ -634,13 +653,8 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
         for (int q = 0; q < 2; ++q)
             if (cnt[q] > 0 && st[q] >= base && st[q] < base + 64) own[st[q] - base] = 2 * lane + q;
         wave_lds_sync();
-        int o = own[lane];
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int u = __shfl_up(o, (unsigned)off, 64);
-            if (lane >= off) o = max(o, u);
-        }
-        o = max(o, carry);
+        int o = wave_scan_max(own[lane]);
+        o = min(max(o, carry), n - 1);
         carry = __shfl(o, 63, 64);
         const int j = base + lane;
         if (j < total) {
