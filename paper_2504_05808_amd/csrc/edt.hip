@@ -82,7 +82,8 @@ edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, 
 // One line pass along y (AXIS = 1, input g, squared here) or z (AXIS = 2, input d2).
 // A block owns 64 consecutive x and LINE_T consecutive positions along the pass
 // axis; it stages the values of those positions plus LINE_H on each side in LDS
-// (coalesced row loads), each packed with two run-boundary bits: LINE_BLK_DN when
+// (coalesced row loads), each packed with two run-boundary bits (derived from the
+// labels, staged first in the same words): LINE_BLK_DN when
 // the position's label differs from the next one's (a search walking down from
 // the next position stops there), LINE_BLK_UP when it differs from the previous
 // one's; positions outside the image count as background.  Each voxel's outward
@@ -95,8 +96,10 @@ template <typename L, int AXIS, typename F>
 __global__ void __launch_bounds__(512)
 edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __restrict__ out,
               int nx, int ny, int nz) {
-    __shared__ L s_lab[LINE_ROWS * 64];
+    // one LDS word per staged position: first the labels (to derive the boundary
+    // bits), then the value with its bits; the values wait in registers meanwhile
     __shared__ uint32_t s_val[LINE_ROWS * 64];
+    constexpr int RPT = LINE_ROWS / 8;                     // staged rows per thread
     const int tx = threadIdx.x, ty = threadIdx.y;          // 64 x 8
     const int x = blockIdx.x * 64 + tx;
     const int n = AXIS == 1 ? ny : nz;
@@ -105,7 +108,10 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
     const ptrdiff_t stride = AXIS == 1 ? (ptrdiff_t)nx : (ptrdiff_t)nx * ny;
     const size_t base = AXIS == 1 ? (size_t)o * ny * nx : (size_t)o * nx;   // (a = 0, x = 0)
     const int lo = max(0, a0 - LINE_H), hi = min(n, a0 + LINE_T + LINE_H);
-    for (int r = ty; r < LINE_ROWS; r += 8) {
+    uint32_t vals[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = ty + 8 * q;
         const int a = a0 - LINE_H + r;
         L lv = L(0);
         int fv = 0;
@@ -114,29 +120,33 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             lv = lab[i];
             fv = (int)f[i];
         }
-        s_lab[r * 64 + tx] = lv;
-        s_val[r * 64 + tx] = (uint32_t)(AXIS == 1 ? fv * fv : fv);
+        s_val[r * 64 + tx] = (uint32_t)lv;
+        vals[q] = (uint32_t)(AXIS == 1 ? fv * fv : fv);
     }
     __syncthreads();
-    for (int r = ty; r < LINE_ROWS; r += 8) {
-        const L lv = s_lab[r * 64 + tx];
-        const bool dn = r + 1 >= LINE_ROWS || s_lab[(r + 1) * 64 + tx] != lv;
-        const bool up = r == 0 || s_lab[(r - 1) * 64 + tx] != lv;
-        s_val[r * 64 + tx] |= (dn ? LINE_BLK_DN : 0u) | (up ? LINE_BLK_UP : 0u);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = ty + 8 * q;
+        const uint32_t lv = s_val[r * 64 + tx];
+        const bool dn = r + 1 >= LINE_ROWS || s_val[(r + 1) * 64 + tx] != lv;
+        const bool up = r == 0 || s_val[(r - 1) * 64 + tx] != lv;
+        vals[q] |= (dn ? LINE_BLK_DN : 0u) | (up ? LINE_BLK_UP : 0u);
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) s_val[(ty + 8 * q) * 64 + tx] = vals[q];
     __syncthreads();
     if (x >= nx) return;
     for (int r = LINE_H + ty; r < LINE_H + LINE_T; r += 8) {
         const int p = a0 - LINE_H + r;
         if (p >= n) break;
-        const L l = s_lab[r * 64 + tx];
         const size_t i = base + (size_t)p * stride + x;
-        if (l == 0) {
+        const uint32_t w0 = s_val[r * 64 + tx];
+        int best = (int)(w0 & LINE_VAL);
+        if (best == 0) {                                   // background (object values are >= 1)
             out[i] = 0;
             continue;
         }
-        const uint32_t w0 = s_val[r * 64 + tx];
-        int best = (int)(w0 & LINE_VAL);
         bool dlo = true, dhi = true;
         int k = 1;
         // staged range, four steps per round: the eight words are loaded first so
@@ -189,6 +199,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
                 }
             }
         }
+        const L l = k * k < best && (dlo || dhi) ? lab[i] : L(0);
         for (; k * k < best && (dlo || dhi); ++k) {                // beyond the halo
             const int kk = k * k;
             if (dlo) {

@@ -519,7 +519,8 @@ struct TileCtx {
     const uint8_t* reach;  // LDS table of open_reach
     int H, W;              // tile extent
     int ty0, tx0;          // tile origin (absolute)
-    int lstride;           // words per level = H * TILE_STRIDE
+    int lstride;           // words per level = H * TILE_STRIDE + 1 (the odd word staggers
+                           // the levels over the LDS banks)
     unsigned long long* dirty;   // LDS mask of the tile rows painted in the current slice
 };
 
@@ -548,6 +549,16 @@ __device__ __forceinline__ int wave_scan_add(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
     x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_or(uint32_t x) {
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
     return x;
 }
 
@@ -615,7 +626,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
         local += cnt[q];
     }
     const int incl = wave_scan_add(local);
-    const int total = __shfl(incl, 63, 64);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
     {                                               // rows these discs paint
         unsigned long long rows = 0ull;
 #pragma unroll
@@ -629,8 +640,9 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
                 rows |= span << r0;
             }
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) rows |= __shfl_xor(rows, off, 64);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_or((uint32_t)rows), 63);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_or((uint32_t)(rows >> 32)), 63);
+        rows = ((unsigned long long)hi << 32) | lo;
         if (lane == 0 && rows) atomicOr(t.dirty, rows);
     }
     int run = incl - local;
@@ -655,7 +667,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
         wave_lds_sync();
         int o = wave_scan_max(own[lane]);
         o = min(max(o, carry), n - 1);
-        carry = __shfl(o, 63, 64);
+        carry = __builtin_amdgcn_readlane(o, 63);
         const int j = base + lane;
         if (j < total) {
             const int xw = e_x[o];
@@ -715,7 +727,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     const size_t n = (size_t)nx * ny * nz;
     // The table is all zero between slices: every cell a slice uses is cleared by
     // the wave that reads it out.
-    for (int q = tid; q < TILE_LEVELS * tile_y * TILE_STRIDE; q += blockDim.x) M[q] = 0u;
+    for (int q = tid; q < TILE_LEVELS * (tile_y * TILE_STRIDE + 1); q += blockDim.x) M[q] = 0u;
     for (int w = tid; w < REACH_TAB; w += blockDim.x) s_reach[w] = (uint8_t)(w > 0 ? open_reach(w) : 0);
     for (;;) {
         if (tid == 0) {
@@ -742,13 +754,13 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int tt = (int)(item - toff[l]);
         TileCtx t;
         t.M = M;
-        t.disc = (int*)(M + TILE_LEVELS * tile_y * TILE_STRIDE) + wid * (4 * DL_CAP + 64);
+        t.disc = (int*)(M + TILE_LEVELS * (tile_y * TILE_STRIDE + 1)) + wid * (4 * DL_CAP + 64);
         t.reach = s_reach;
         t.ty0 = y0 + (tt / tiles_x) * tile_y;
         t.tx0 = x0 + (tt % tiles_x) * TILE_X;
         t.H = min(tile_y, y1 - t.ty0);
         t.W = min(TILE_X, x1 - t.tx0);
-        t.lstride = t.H * TILE_STRIDE;
+        t.lstride = t.H * TILE_STRIDE + 1;
         const int sy0 = max(y0, t.ty0 - R), sy1 = min(y1, t.ty0 + t.H + R);
         const int sx0 = max(x0, t.tx0 - R), sx1 = min(x1, t.tx0 + t.W + R);
         const int nlev = 32 - __clz(min(t.W, 2 * R + 1));   // levels 0 .. floor(log2(span))
@@ -1001,13 +1013,13 @@ size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label) {
 // Dynamic LDS of a paint block: the sparse table for `rows` tile rows plus one disc
 // list per wave.
 static size_t paint_lds(int rows, int threads) {
-    return (size_t)TILE_LEVELS * rows * TILE_STRIDE * sizeof(uint32_t) +
+    return (size_t)TILE_LEVELS * (rows * TILE_STRIDE + 1) * sizeof(uint32_t) +
            (size_t)(threads / 64) * (4 * DL_CAP + 64) * sizeof(int);
 }
 
 // Tile rows of the paint pass: 64 when the device lets one 1024-thread block hold
 // the 64-row table (7 levels x 64 x 65 words = 116,480 B) and its wave lists, else 32.
-constexpr size_t PAINT_DYN64 = (size_t)TILE_LEVELS * 64 * TILE_STRIDE * sizeof(uint32_t) +
+constexpr size_t PAINT_DYN64 = (size_t)TILE_LEVELS * (64 * TILE_STRIDE + 1) * sizeof(uint32_t) +
                                (size_t)(PAINT_THREADS / 64) * (4 * DL_CAP + 64) * sizeof(int);
 
 int paint_tile_rows(lt_ctx* ctx) {
