@@ -50,20 +50,33 @@ size_t pipeline_measures_offset(const Geom& g, uint32_t max_label) {
     return (thickness_scratch_bytes(g, max_label) + 255) & ~size_t(255);
 }
 
-size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label) {
+// Fused pipeline scratch: [EDT | thickness + measures] overlapping from offset 0
+// (EDT finishes before thickness starts), then the bounding boxes, which the EDT x
+// pass writes and the thickness pass reads.
+static size_t pipeline_boxes_offset(const Geom& g, uint32_t max_label) {
     size_t b = edt_scratch_bytes(g);
     b = std::max(b, pipeline_measures_offset(g, max_label) + measures_scratch_bytes(max_label));
     return (b + 255) & ~size_t(255);
+}
+
+size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label) {
+    const size_t boxes = 6 * ((size_t)max_label + 1) * sizeof(int32_t);
+    return pipeline_boxes_offset(g, max_label) + ((boxes + 255) & ~size_t(255));
 }
 
 lt_status launch_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
                           int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out, void* scratch,
                           hipStream_t s) {
     void* mscr = (char*)scratch + pipeline_measures_offset(g, max_label);
-    lt_status st = g.n > 0 ? launch_edt(ctx, labels, dt, g, dist_sq, scratch, s) : LT_OK;
+    int32_t* bb = (int32_t*)((char*)scratch + pipeline_boxes_offset(g, max_label));
+    const BoxTarget box{bb, max_label + 1, max_label};
+    lt_status st = LT_OK;
+    if (g.n > 0 && !(st = launch_init_boxes(ctx, bb, max_label + 1, s)))
+        st = launch_edt(ctx, labels, dt, g, dist_sq, scratch, s, &box);
     MeasureSums sums;
     if (!st) st = launch_measures_zero(ctx, max_label, out, mscr, s, &sums);
-    if (!st && g.n > 0) st = launch_thickness(ctx, labels, dt, g, dist_sq, max_label, lt_sq, scratch, s, &sums);
+    if (!st && g.n > 0)
+        st = launch_thickness(ctx, labels, dt, g, dist_sq, max_label, lt_sq, scratch, s, &sums, bb);
     if (!st) st = launch_measures_finish(ctx, labels, dt, g, lt_sq, max_label, out, mscr, s);
     return st;
 }

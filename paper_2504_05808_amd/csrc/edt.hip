@@ -21,15 +21,34 @@ namespace lt {
 // and ends.  A voxel's run [s, e] is found from the nearest start at or before it
 // and the nearest end at or after it -- in its own chunk via bit scans, otherwise
 // from the per-chunk extremes kept in LDS -- and g = min(x - s + 1, e - x + 1).
-template <typename L>
+// With BOX, the first voxel of every object run also merges (z, y, run) into the
+// block's label table in LDS (bounding boxes of the fused pipeline); a block walks
+// consecutive slices of one row index y, so an object's runs meet in few blocks,
+// and the table is flushed to the global boxes once per block.
+constexpr int XBOX_TAB = 128;
+
+template <typename L, bool BOX>
 __global__ void __launch_bounds__(1024)
-edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, int nz, uint32_t* err) {
+edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, int nz, uint32_t* err,
+           BoxTarget box, int zper) {
     __shared__ unsigned long long s_start[ROW_MAX_CHUNKS], s_end[ROW_MAX_CHUNKS];
+    __shared__ uint32_t s_key[BOX ? XBOX_TAB : 1];
+    __shared__ int s_bb[6][BOX ? XBOX_TAB : 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     const int chunks = (nx + 63) >> 6;
-  for (int z = blockIdx.z; z < nz; z += gridDim.z) {
-    const size_t row = (size_t)z * ny + blockIdx.y;
+    const int y = blockIdx.y;
+    if (BOX) {
+        for (int t = threadIdx.x; t < XBOX_TAB; t += blockDim.x) {
+            s_key[t] = 0u;
+            s_bb[0][t] = s_bb[2][t] = s_bb[4][t] = 0x7fffffff;
+            s_bb[1][t] = s_bb[3][t] = s_bb[5][t] = -1;
+        }
+        __syncthreads();
+    }
+    const int zb = blockIdx.z * zper, ze = min(nz, zb + zper);
+  for (int z = zb; z < ze; ++z) {
+    const size_t row = (size_t)z * ny + y;
     const L* r = lab + row * nx;
     for (int c = wid; c < chunks; c += nw) {
         const int x = c * 64 + lane;
@@ -72,11 +91,51 @@ edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, 
                 e0 = cc * 64 + __ffsll(s_end[cc]) - 1;
             }
             out = min(x - s0 + 1, e0 - x + 1);
+            if (BOX && x == s0) {                          // first voxel of its run
+                if ((uint64_t)l > box.max_label) {
+                    atomicOr(err, ERR_LABEL);
+                } else if (!label_negative(l)) {
+                    const uint32_t u = (uint32_t)l;
+                    const int slot = lds_slot<XBOX_TAB>(s_key, u);
+                    if (slot >= 0) {
+                        atomicMin(&s_bb[0][slot], z);
+                        atomicMax(&s_bb[1][slot], z);
+                        atomicMin(&s_bb[2][slot], y);
+                        atomicMax(&s_bb[3][slot], y);
+                        atomicMin(&s_bb[4][slot], s0);
+                        atomicMax(&s_bb[5][slot], e0);
+                    } else {
+                        atomicMin(&box.bb[0 * box.nlab + u], z);
+                        atomicMax(&box.bb[1 * box.nlab + u], z);
+                        atomicMin(&box.bb[2 * box.nlab + u], y);
+                        atomicMax(&box.bb[3 * box.nlab + u], y);
+                        atomicMin(&box.bb[4 * box.nlab + u], s0);
+                        atomicMax(&box.bb[5 * box.nlab + u], e0);
+                    }
+                }
+            }
         }
         g[row * nx + x] = (uint16_t)out;
     }
     __syncthreads();                                     // the masks are reused by the next row
   }
+    if (BOX) {
+        for (int t = threadIdx.x; t < XBOX_TAB; t += blockDim.x) {
+            const uint32_t u = s_key[t];
+            if (u == 0u) continue;
+            atomicMin(&box.bb[0 * box.nlab + u], s_bb[0][t]);
+            atomicMax(&box.bb[1 * box.nlab + u], s_bb[1][t]);
+            atomicMin(&box.bb[2 * box.nlab + u], s_bb[2][t]);
+            atomicMax(&box.bb[3 * box.nlab + u], s_bb[3][t]);
+            atomicMin(&box.bb[4 * box.nlab + u], s_bb[4][t]);
+            atomicMax(&box.bb[5 * box.nlab + u], s_bb[5][t]);
+        }
+    }
+}
+
+__global__ void init_boxes(int32_t* bb, uint32_t nlab) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nlab) init_box(bb, nlab, l);
 }
 
 // One line pass along y (AXIS = 1, input g, squared here) or z (AXIS = 2, input d2).
@@ -232,7 +291,7 @@ size_t edt_scratch_bytes(const Geom& g) {
 
 template <typename L>
 static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* dist, void* scratch,
-                           hipStream_t s) {
+                           hipStream_t s, const BoxTarget* box) {
     // scratch: g (uint16) then d2 (int32, 3D only)
     const size_t gbytes = (g.n * sizeof(uint16_t) + 255) & ~size_t(255);
     uint16_t* gx = (uint16_t*)scratch;
@@ -241,7 +300,14 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
         ProfScope _p(ctx, s, "edt_pass_x");
         const int threads = min(1024, ((g.nx + 63) / 64) * 64);
         const int gz = loop_extent(g.nz, g.ny, ctx);
-        edt_pass_x<L><<<dim3(1, g.ny, gz), threads, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err);
+        const int zper = (g.nz + gz - 1) / gz;
+        const int nzb = (g.nz + zper - 1) / zper;
+        if (box)
+            edt_pass_x<L, true><<<dim3(1, g.ny, nzb), threads, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err, *box,
+                                                                     zper);
+        else
+            edt_pass_x<L, false><<<dim3(1, g.ny, nzb), threads, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err,
+                                                                      BoxTarget{nullptr, 0, 0}, zper);
     }
     const dim3 lblock(64, 8);
     const int bx = (g.nx + 63) / 64;
@@ -264,13 +330,19 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
 }
 
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, int32_t* dist_sq,
-                     void* scratch, hipStream_t s) {
+                     void* scratch, hipStream_t s, const BoxTarget* box) {
     switch (dt) {
-        case LT_U16: return edt_typed(ctx, (const uint16_t*)labels, g, dist_sq, scratch, s);
-        case LT_I32: return edt_typed(ctx, (const int32_t*)labels, g, dist_sq, scratch, s);
-        case LT_U32: return edt_typed(ctx, (const uint32_t*)labels, g, dist_sq, scratch, s);
+        case LT_U16: return edt_typed(ctx, (const uint16_t*)labels, g, dist_sq, scratch, s, box);
+        case LT_I32: return edt_typed(ctx, (const int32_t*)labels, g, dist_sq, scratch, s, box);
+        case LT_U32: return edt_typed(ctx, (const uint32_t*)labels, g, dist_sq, scratch, s, box);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
+}
+
+lt_status launch_init_boxes(lt_ctx* ctx, int32_t* bb, uint32_t nlab, hipStream_t s) {
+    ProfScope _p(ctx, s, "init_boxes");
+    init_boxes<<<(nlab + 255) / 256, 256, 0, s>>>(bb, nlab);
+    return hip_check(hipGetLastError(), "box init launch");
 }
 
 }  // namespace lt

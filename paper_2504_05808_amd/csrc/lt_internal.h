@@ -106,12 +106,23 @@ lt_status hip_check(hipError_t e, const char* what);
 lt_status ensure_scratch(lt_ctx* ctx, size_t bytes);
 lt_status geom_from(int ndim, const int64_t* shape, Geom* g);
 
+// Where the EDT x pass records bounding boxes (fused pipeline): device boxes of
+// nlab labels, and the largest valid label (larger labels set ERR_LABEL).
+struct BoxTarget {
+    int32_t* bb;
+    uint32_t nlab;
+    uint32_t max_label;
+};
+
 // Launchers (edt.hip, thickness.hip, measures.hip).  All are stream-ordered, use the
 // caller's scratch region (at least *_scratch_bytes bytes, 256-byte aligned) and
 // allocate nothing, so they can be captured into a graph.
 size_t edt_scratch_bytes(const Geom& g);
+// With `box` set, the x pass also records the per-label bounding boxes (fused
+// pipeline; the boxes must have been emptied first).
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
-                     int32_t* dist_sq, void* scratch, hipStream_t s);
+                     int32_t* dist_sq, void* scratch, hipStream_t s, const BoxTarget* box = nullptr);
+lt_status launch_init_boxes(lt_ctx* ctx, int32_t* bb, uint32_t nlab, hipStream_t s);
 size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label);
 int paint_tile_rows(lt_ctx* ctx);
 // Device arrays of the per-object integer sums (zeroed by launch_measures_zero).
@@ -124,9 +135,12 @@ struct MeasureSums {
 };
 // With `sums` set, the paint pass also accumulates the per-object sums of the
 // measures (the fused form); launch_measures_finish then completes them.
+// With `boxes` set, the bounding boxes come from the caller (recorded by the EDT x
+// pass) and the box pass is skipped.
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           void* scratch, hipStream_t s, const MeasureSums* sums = nullptr);
+                           void* scratch, hipStream_t s, const MeasureSums* sums = nullptr,
+                           int32_t* boxes = nullptr);
 size_t measures_scratch_bytes(uint32_t max_label);
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                           const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
@@ -201,6 +215,28 @@ template <typename L>
 __device__ __forceinline__ bool label_negative(L v) {
     if constexpr (sizeof(L) == 4 && L(-1) < L(0)) return v < 0;
     else return false;
+}
+
+// Per-block label table in LDS: open addressing with linear probing on the key
+// (label, 0 = empty).  Returns the slot of `l`, inserting it, or -1 when the table
+// is full (the caller then updates global memory directly).
+template <int CAP>
+__device__ __forceinline__ int lds_slot(uint32_t* keys, uint32_t l) {
+    int h = (int)((l * 2654435761u) >> 7) & (CAP - 1);
+    for (int probe = 0; probe < CAP; ++probe) {
+        const uint32_t k = atomicCAS(&keys[h], 0u, l);
+        if (k == 0u || k == l) return h;
+        h = (h + 1) & (CAP - 1);
+    }
+    return -1;
+}
+
+// Empty bounding box of label l: bb layout [zmin, zmax, ymin, ymax, xmin, xmax][nlab].
+__device__ __forceinline__ void init_box(int32_t* bb, uint32_t nlab, uint32_t l) {
+    for (int k = 0; k < 3; ++k) {
+        bb[(2 * k) * nlab + l] = 0x7fffffff;
+        bb[(2 * k + 1) * nlab + l] = -1;
+    }
 }
 
 }  // namespace lt

@@ -40,25 +40,8 @@ __global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uin
     for (size_t c = l; c < ncol; c += (size_t)gridDim.x * blockDim.x) colmax[c] = 0;
     if (l == 0) *gmax = 0u;
     if (l >= nlab) return;
-    for (int k = 0; k < 3; ++k) {
-        bb[(2 * k) * nlab + l] = 0x7fffffff;
-        bb[(2 * k + 1) * nlab + l] = -1;
-    }
+    if (bb) init_box(bb, nlab, l);
     maxd[l] = 0;
-}
-
-// Per-block label table in LDS: open addressing with linear probing on the key
-// (label, 0 = empty).  Returns the slot of `l`, inserting it, or -1 when the table
-// is full (the caller then updates global memory directly).
-template <int CAP>
-__device__ __forceinline__ int lds_slot(uint32_t* keys, uint32_t l) {
-    int h = (int)((l * 2654435761u) >> 7) & (CAP - 1);
-    for (int probe = 0; probe < CAP; ++probe) {
-        const uint32_t k = atomicCAS(&keys[h], 0u, l);
-        if (k == 0u || k == l) return h;
-        h = (h + 1) & (CAP - 1);
-    }
-    return -1;
 }
 
 constexpr int BB_TAB = 128;           // labels per block table
@@ -1041,12 +1024,12 @@ int paint_tile_rows(lt_ctx* ctx) {
 template <typename L>
 static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* D,
                                  uint32_t max_label, int32_t* lt, void* scratch, hipStream_t s,
-                                 const MeasureSums* sums) {
+                                 const MeasureSums* sums, int32_t* boxes) {
     const MeasureSums none{nullptr, nullptr, nullptr, nullptr, nullptr};
     const MeasureSums ms = sums ? *sums : none;
     const ThickLayout lay = thick_layout(g, max_label);
     char* base = (char*)scratch;
-    int32_t* bb = (int32_t*)(base + lay.bb);
+    int32_t* bb = boxes ? boxes : (int32_t*)(base + lay.bb);
     int32_t* maxd = (int32_t*)(base + lay.maxd);
     uint32_t* toff = (uint32_t*)(base + lay.toff);
     uint32_t* counter = (uint32_t*)(base + lay.counter);
@@ -1062,11 +1045,10 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     {
         ProfScope _p(ctx, s, "init_label_arrays");
         const size_t work = std::max((size_t)nlab, std::min(ncol, (size_t)1 << 20));
-        init_label_arrays<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(bb, maxd, nlab, gmax, colmax, ncol);
+        init_label_arrays<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(boxes ? nullptr : bb, maxd, nlab, gmax,
+                                                                          colmax, ncol);
     }
-    const dim3 block(256);
-    const dim3 grid((g.nx + 255) / 256, g.ny, g.nz);
-    {
+    if (!boxes) {
         ProfScope _p(ctx, s, "bbox_runs");
         bbox_runs<L><<<dim3(1, (g.ny + BB_ROWS_Y - 1) / BB_ROWS_Y, (g.nz + BB_ROWS_Z - 1) / BB_ROWS_Z), 1024, 0,
                        s>>>(lab, g.nx, g.ny, g.nz, max_label, bb, nlab, ctx->d_err);
@@ -1086,7 +1068,7 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         }
     } else {
         ProfScope _p(ctx, s, "pixels2d");
-        pixels2d<L><<<dim3((g.nx + 255) / 256, g.ny), block, 0, s>>>(
+        pixels2d<L><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(
             lab, D, g.nx, g.ny, max_label, ctx->d_prune2, zf, lt, maxd);
     }
     const int tile_y = paint_tile_rows(ctx);
@@ -1115,14 +1097,17 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
 
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           void* scratch, hipStream_t s, const MeasureSums* sums) {
+                           void* scratch, hipStream_t s, const MeasureSums* sums, int32_t* boxes) {
     switch (dt) {
         case LT_U16:
-            return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums);
+            return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums,
+                                   boxes);
         case LT_I32:
-            return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums);
+            return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums,
+                                   boxes);
         case LT_U32:
-            return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums);
+            return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums,
+                                   boxes);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

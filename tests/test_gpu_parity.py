@@ -211,6 +211,20 @@ def test_label_above_max_label_sets_error(gpu):
     lt.default_context().sync_status()          # the word was cleared
 
 
+def test_label_above_max_label_sets_error_in_fused_call(gpu):
+    """The fused call finds out-of-range labels while it records the boxes."""
+    torch, lt = gpu
+    lab = np.zeros((9, 10, 70), dtype=np.uint16)
+    lab[2:5, 2:5, 60:68] = 3
+    lab[6, 7, 1:4] = 11
+    t = torch.from_numpy(lab).cuda()
+    lt.pipeline(t, 4)
+    with pytest.raises(lt.LTError) as e:
+        lt.default_context().sync_status()
+    assert e.value.status == 6
+    lt.default_context().sync_status()
+
+
 def test_deterministic_repeat(gpu):
     lab, _ = synth.cfg2()
     a = run_gpu(gpu, lab)
