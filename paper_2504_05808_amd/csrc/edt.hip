@@ -34,7 +34,7 @@ edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, 
     __shared__ unsigned long long s_start[ROW_MAX_CHUNKS], s_end[ROW_MAX_CHUNKS];
     __shared__ uint32_t s_key[BOX ? XBOX_TAB : 1];
     __shared__ int s_bb[6][BOX ? XBOX_TAB : 1];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int chunks = (nx + 63) >> 6;
     const int y = blockIdx.y;
@@ -151,6 +151,11 @@ __global__ void init_boxes(int32_t* bb, uint32_t nlab) {
 constexpr int LINE_T = 64, LINE_H = 32, LINE_ROWS = LINE_T + 2 * LINE_H;
 constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LINE_BLK_UP - 1u;
 
+// Value a staged word offers a search walking down (up) to it: its value, or 0 when
+// the word carries the boundary bit of that direction (a site of another label).
+__device__ __forceinline__ int line_down(uint32_t w) { return (int)(w & LINE_VAL) & ~((int)w >> 31); }
+__device__ __forceinline__ int line_up(uint32_t w) { return (int)(w & LINE_VAL) & ~((int)(w << 1) >> 31); }
+
 template <typename L, int AXIS, typename F>
 __global__ void __launch_bounds__(512)
 edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __restrict__ out,
@@ -206,79 +211,45 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             out[i] = 0;
             continue;
         }
-        bool dlo = true, dhi = true;
+        // A position past a label boundary offers k^2 (its run ends there); once that
+        // happens best <= k^2 and every later candidate, at least (k + 1)^2, loses, so
+        // the search needs no per-direction stop: it ends when k^2 reaches best.
         int k = 1;
         // staged range, four steps per round: the eight words are loaded first so
         // that their latencies overlap; the steps are then applied in order
-        while (k * k < best && (dlo || dhi) && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
+        while (k * k < best && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
             uint32_t wl[4], wh[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 wl[u] = s_val[(r - k - u) * 64 + tx];
                 wh[u] = s_val[(r + k + u) * 64 + tx];
             }
-            // branch-free steps: a step is active while k^2 < best (tested once per
-            // step, as in the plain loop); a boundary bit ends that direction with
-            // candidate k^2, any other position offers k^2 + its value
+            int kk = k * k;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int kk = (k + u) * (k + u);
-                const bool act = kk < best;
-                const bool lb = (wl[u] & LINE_BLK_DN) != 0u;   // label(p-k) != label(p-k+1)
-                const bool hb = (wh[u] & LINE_BLK_UP) != 0u;   // label(p+k) != label(p+k-1)
-                const int cl = lb ? kk : kk + (int)(wl[u] & LINE_VAL);
-                const int ch = hb ? kk : kk + (int)(wh[u] & LINE_VAL);
-                const bool ul = act && dlo, uh = act && dhi;
-                best = ul ? min(best, cl) : best;
-                best = uh ? min(best, ch) : best;
-                dlo = dlo && !(ul && lb);
-                dhi = dhi && !(uh && hb);
+                best = min(best, kk + min(line_down(wl[u]), line_up(wh[u])));
+                kk += 2 * (k + u) + 1;
             }
             k += 4;
         }
-        for (; k * k < best && (dlo || dhi); ++k) {
+        for (; k * k < best; ++k) {
             if (r - k < 0 || r + k >= LINE_ROWS) break;           // leave the staged range
-            const int kk = k * k;
-            if (dlo) {
-                const uint32_t w = s_val[(r - k) * 64 + tx];
-                if (w & LINE_BLK_DN) {
-                    best = min(best, kk);
-                    dlo = false;
-                } else {
-                    best = min(best, kk + (int)(w & LINE_VAL));
-                }
-            }
-            if (dhi) {
-                const uint32_t w = s_val[(r + k) * 64 + tx];
-                if (w & LINE_BLK_UP) {
-                    best = min(best, kk);
-                    dhi = false;
-                } else {
-                    best = min(best, kk + (int)(w & LINE_VAL));
-                }
-            }
+            const uint32_t wl = s_val[(r - k) * 64 + tx], wh = s_val[(r + k) * 64 + tx];
+            best = min(best, k * k + min(line_down(wl), line_up(wh)));
         }
-        const L l = k * k < best && (dlo || dhi) ? lab[i] : L(0);
-        for (; k * k < best && (dlo || dhi); ++k) {                // beyond the halo
+        const L l = k * k < best ? lab[i] : L(0);
+        for (; k * k < best; ++k) {                                // beyond the halo
             const int kk = k * k;
-            if (dlo) {
-                if (p - k < 0 || lab[i - k * stride] != l) {
-                    best = min(best, kk);
-                    dlo = false;
-                } else {
-                    const int v = (int)f[i - k * stride];
-                    best = min(best, kk + (AXIS == 1 ? v * v : v));
-                }
+            int cl = kk, ch = kk;
+            if (p - k >= 0 && lab[i - k * stride] == l) {
+                const int v = (int)f[i - k * stride];
+                cl += AXIS == 1 ? v * v : v;
             }
-            if (dhi) {
-                if (p + k >= n || lab[i + k * stride] != l) {
-                    best = min(best, kk);
-                    dhi = false;
-                } else {
-                    const int v = (int)f[i + k * stride];
-                    best = min(best, kk + (AXIS == 1 ? v * v : v));
-                }
+            if (p + k < n && lab[i + k * stride] == l) {
+                const int v = (int)f[i + k * stride];
+                ch += AXIS == 1 ? v * v : v;
             }
+            best = min(best, min(cl, ch));
         }
         out[i] = best;
     }

@@ -35,7 +35,8 @@ constexpr int ROW_MAX_CHUNKS = 32;
 // the slice minus the centre's z), 29..31 (plane 0 only) number of entries.  The
 // count 7 marks a front longer than ZF_PLANES: with ZF_SPILL set, bits 16..23 hold
 // its length and bits 0..15 its offset in the spill region of the front pass's
-// block that owns the voxel; without it, the column is rescanned.
+// block (row of 64 columns, z chunk) that owns the voxel; without it, the column is
+// rescanned.
 constexpr uint32_t ZF_D_BITS = 19;
 constexpr uint32_t ZF_D_MASK = (1u << ZF_D_BITS) - 1u;
 constexpr uint32_t ZF_DZ_SHIFT = 19;
@@ -43,9 +44,9 @@ constexpr uint32_t ZF_DZ_MASK = 1023u;
 constexpr uint32_t ZF_N_SHIFT = 29;
 constexpr int ZF_PLANES = 4;
 constexpr uint32_t ZF_SPILL = 1u << 28;
-// Spill words per (64 x 4 column block, slice) of the front pass: half a word per
+// Spill words per (row of 64 columns, slice) of the front pass: half a word per
 // voxel; a block whose long fronts need more falls back to rescans.
-constexpr int SPILL_PER_SLICE = 128;
+constexpr int SPILL_ROW_SLICE = 32;
 
 // Column-list entry (3D): (D << 11) | z.
 constexpr uint32_t CL_Z_BITS = 11;

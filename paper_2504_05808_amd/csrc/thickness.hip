@@ -67,7 +67,7 @@ bbox_runs(const L* __restrict__ lab, int nx, int ny, int nz, uint32_t max_label,
         s_bb[1][t] = s_bb[3][t] = s_bb[5][t] = -1;
     }
     __syncthreads();
-    const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    const int lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6), nw = blockDim.x >> 6;
     const int chunks = (nx + 63) >> 6;                   // <= 64
     const int y0 = blockIdx.y * BB_ROWS_Y, z0 = blockIdx.z * BB_ROWS_Z;
     const int rows = BB_ROWS_Y * BB_ROWS_Z;
@@ -267,152 +267,247 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     if (cmax > 0) atomicMax(&colmax[(size_t)y * nx + x], cmax);
 }
 
+// ------------------------------------------------------------------ wave helpers
+
+// Inclusive scans over the 64 lanes of a wave with DPP moves (VALU only, no LDS
+// traffic): row_shr by 1, 2, 4, 8 within each row of 16 lanes, then row_bcast:15
+// (rows 1 and 3 take the last lane of the row before) and row_bcast:31 (rows 2 and 3
+// take lane 31).  Lanes without a source take the identity.
+__device__ __forceinline__ int wave_scan_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_or(uint32_t x) {
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    return x;
+}
+
+__device__ __forceinline__ int wave_scan_max(int x) {                // identity -1
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ 3D z-fronts
 
-constexpr int FR_CAP = 48;          // kept centres per thread held in LDS
+constexpr int FZ_H = 32;            // staged slices on each side of the chunk
+constexpr int FZ_CAP = 128;         // listed centres per column (two per lane)
+constexpr int FZ_LIST = FZ_CAP + 4; // list words per wave (zero padding for 4-wide reads)
+constexpr int FZ_STRIDE = 65;       // staging-tile row stride in words (conflict-free columns)
 
-// One thread per (column, chunk of `chunk` slices).  The kept centres of the
-// column within the chunk grown by the column's reach R (of its largest kept D) are
-// gathered (batched loads)
-// into the thread's LDS list and ordered by D; then for each slice of the chunk
-// one scan of that list yields the Pareto front over (value D, residual
-// D - dz^2 > 0), stored in the front planes or, when longer than the planes, in
-// the block's spill region.  A list that would exceed FR_CAP, or a spill region
-// that is full, marks the fronts "rescan" (count 7 without ZF_SPILL); the paint
-// pass then takes every centre of the column instead (same result).
+static size_t fronts3d_lds(int chunk) {
+    return (size_t)(4 * 2 * FZ_LIST + (chunk + 2 * FZ_H) * FZ_STRIDE) * sizeof(uint32_t);
+}
+
+// One block per (row y, 64 columns, chunk of `chunk` slices), four waves.  The
+// kept-centre field of the block's columns over the chunk +- the largest column
+// reach (at most FZ_H) is staged in LDS with coalesced row loads.  Each wave then
+// takes whole columns, lanes along z: the column's kept centres within the chunk
+// grown by the column's own reach R are compacted (ballots) into the wave's list,
+// ordered by D (each entry's rank counted against the whole list), and held two per
+// lane in registers.  For each slice (one per lane) a scan of the list, read
+// wave-uniformly with readlane, yields the Pareto front over (value D, residual
+// D - dz^2 > 0): by decreasing D, a group of equal D contributes its largest
+// residual when that exceeds every residual of larger D, and a lane stops at the
+// first D not above that maximum; slices no listed ball reaches take no part.  The
+// first ZF_PLANES members go to the planes (plane 0 back through the staging tile,
+// written out coalesced); a longer front is written whole to the block's spill
+// region (second scan).  A list longer than FZ_CAP, or a full spill region, marks
+// the fronts "rescan" (count 7 without ZF_SPILL): the paint pass then takes every
+// centre of the column (same result).
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
-    __shared__ uint32_t s_list[256 * FR_CAP];
-    __shared__ uint32_t s_used;                    // words of the block's spill region in use
-    const int tid = threadIdx.y * 64 + threadIdx.x;
-    if (tid == 0) s_used = 0u;
-    __syncthreads();
-    uint32_t* list = s_list + tid;                 // stride 256: lane-interleaved, no bank conflicts
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    if (x >= nx || y >= ny) return;
-    const uint32_t cap = (uint32_t)(SPILL_PER_SLICE * chunk);
-    uint32_t* region = spill + ((size_t)(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * cap;
+    extern __shared__ __align__(16) uint32_t S[];
+    __shared__ int s_cm[64];
+    __shared__ int s_hb;
+    __shared__ uint32_t s_used;                       // words of the block's spill region in use
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);    // wave-uniform, in a scalar register
+    const int x0 = blockIdx.x * 64, y = blockIdx.y;
+    const int W = min(64, nx - x0);
     const int c0 = blockIdx.z * chunk, c1 = min(nz, c0 + chunk);
     const size_t plane = (size_t)ny * nx;
-    const size_t col = (size_t)y * nx + x;
-    const int cm = colmax[col];
-    if (cm == 0) {                                       // no kept centre in the column
-        for (int z = c0; z < c1; ++z) zf[(size_t)z * plane + col] = 0u;
-        return;
-    }
-    const int R = open_reach(cm);                        // no ball of the column reaches farther
-    const int zlo = max(0, c0 - R), zhi = min(nz, c1 + R);
     const size_t n = plane * nz;
-    int cnt = 0;
-    bool full = false;
-    for (int zb = zlo; zb < zhi; zb += 8) {
-        int v[8];
+    const size_t rowi = (size_t)y * nx + x0;          // column of lane 0
+    if (wid == 0) {
+        const int cm = lane < W ? colmax[rowi + lane] : 0;
+        s_cm[lane] = cm;
+        int r = cm > 0 ? open_reach(cm) : 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = zb + u < zhi ? kd[(size_t)(zb + u) * plane + col] : 0;
+        for (int off = 32; off >= 1; off >>= 1) r = max(r, __shfl_xor(r, off, 64));
+        if (lane == 0) {
+            s_hb = min(r, FZ_H);
+            s_used = 0u;
+        }
+    }
+    __syncthreads();
+    const int hb = s_hb;
+    const int zs = c0 - hb;                           // first staged slice (may be < 0)
+    const int rows = (c1 - c0) + 2 * hb;
+    uint32_t* tile = S + 4 * 2 * FZ_LIST;
+    for (int q0 = wid; q0 < rows; q0 += 32) {         // eight rows in flight per wave
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 4 * u, z = zs + q;
+            v[u] = (q < rows && z >= 0 && z < nz && lane < W) ? (uint32_t)kd[(size_t)z * plane + rowi + lane] : 0u;
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (v[u] > 0) {
-                if (cnt < FR_CAP) list[cnt * 256] = ((uint32_t)v[u] << CL_Z_BITS) | (uint32_t)(zb + u);
-                else full = true;
-                ++cnt;
-            }
+            if (q0 + 4 * u < rows) tile[(q0 + 4 * u) * FZ_STRIDE + lane] = v[u];
     }
-    if (full) {
-        for (int z = c0; z < c1; ++z) zf[(size_t)z * plane + col] = 7u << ZF_N_SHIFT;
-        return;
-    }
-    // order the list by D, largest first (insertion sort; lists are short)
-    for (int j = 1; j < cnt; ++j) {
-        const uint32_t e = list[j * 256];
-        int q = j - 1;
-        while (q >= 0 && list[q * 256] < e) {            // the key sits in the high bits
-            list[(q + 1) * 256] = list[q * 256];
-            --q;
-        }
-        list[(q + 1) * 256] = e;
-    }
-    // slices of the chunk that some listed ball reaches (chunk <= 128: two words)
-    uint64_t cov[2] = {0ull, 0ull};
-    for (int j = 0; j < cnt; ++j) {
-        const uint32_t e = list[j * 256];
-        const int r = open_reach((int)(e >> CL_Z_BITS)), zc = (int)(e & CL_Z_MASK);
-        const int a = max(zc - r, c0) - c0, b = min(zc + r, c1 - 1) - c0;
-        for (int w = 0; w < 2; ++w) {
-            const int lo = max(a, 64 * w), hi = min(b, 64 * w + 63);
-            if (lo <= hi) {
-                const int len = hi - lo + 1;
-                const uint64_t bits = len == 64 ? ~0ull : ((1ull << len) - 1ull);
-                cov[w] |= bits << (lo - 64 * w);
-            }
-        }
-    }
-    for (int z = c0; z < c1; ++z) {
-        const int zr = z - c0;
-        if (!((cov[zr >> 6] >> (zr & 63)) & 1ull)) {         // no listed ball reaches z
-            zf[(size_t)z * plane + col] = 0u;
+    __syncthreads();
+    uint32_t* list = S + wid * 2 * FZ_LIST;           // compacted, then sorted
+    uint32_t* sorted = list + FZ_LIST;
+    const uint32_t cap = (uint32_t)(SPILL_ROW_SLICE * chunk);
+    uint32_t* region = spill + ((size_t)blockIdx.z * ny + y) * gridDim.x * (size_t)cap + (size_t)blockIdx.x * cap;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int cx = wid; cx < W; cx += 4) {
+        const int cm = __builtin_amdgcn_readfirstlane(s_cm[cx]);
+        uint32_t* out = tile + cx;                    // plane-0 words: out[(z - zs) * FZ_STRIDE]
+        if (cm == 0) {                                // no kept centre in the column
+            for (int z = c0 + lane; z < c1; z += 64) out[(z - zs) * FZ_STRIDE] = 0u;
             continue;
         }
-        // Pareto front over (D, residual b = D - dz^2 > 0): scanning by decreasing
-        // D, a group of equal D contributes its largest b when that exceeds every b
-        // of larger D; the scan ends at the first D not above that running maximum
-        // (its residual and all later ones are smaller).  The first ZF_PLANES members
-        // go to the planes; a longer front is written whole to the block's spill
-        // region (second scan).
-        uint32_t p[ZF_PLANES];
+        const size_t col = rowi + cx;
+        const int R = open_reach(cm);                 // no ball of the column reaches farther
+        const int lo = max(0, c0 - R), hi = min(nz, c1 + R);
+        int cnt = 0;
+        for (int zb = lo; zb < hi; zb += 64) {
+            const int z = zb + lane;
+            int v = 0;
+            if (z < hi) v = (z >= zs && z < zs + rows) ? (int)out[(z - zs) * FZ_STRIDE] : kd[(size_t)z * plane + col];
+            const unsigned long long m = __ballot(v > 0);
+            if (v > 0) {
+                const int pos = cnt + __popcll(m & below);
+                if (pos < FZ_CAP) list[pos] = ((uint32_t)v << CL_Z_BITS) | (uint32_t)z;
+            }
+            cnt += __popcll(m);
+        }
+        if (cnt > FZ_CAP) {
+            for (int z = c0 + lane; z < c1; z += 64) out[(z - zs) * FZ_STRIDE] = 7u << ZF_N_SHIFT;
+            continue;
+        }
+        if (lane < 4) list[cnt + lane] = 0u;          // padding: keys 0 count for no entry
+        wave_lds_sync();
+        // rank of each entry = number of larger keys (keys are distinct: one z each)
+        const uint32_t e0 = lane < cnt ? list[lane] : 0u;
+        const uint32_t e1 = lane + 64 < cnt ? list[lane + 64] : 0u;
+        int r0 = 0, r1 = 0;
+        for (int k = 0; k < cnt; k += 4) {
+            const uint4 q = *(const uint4*)(list + k);
+            r0 += (q.x > e0) + (q.y > e0) + (q.z > e0) + (q.w > e0);
+            r1 += (q.x > e1) + (q.y > e1) + (q.z > e1) + (q.w > e1);
+        }
+        if (lane < cnt) sorted[r0] = e0;
+        if (lane + 64 < cnt) sorted[r1] = e1;
+        wave_lds_sync();
+        const uint32_t s0 = sorted[lane], s1 = sorted[lane + 64];   // entries lane, lane + 64
+        // slices each listed ball reaches, per 64-slice round
+        for (int zr = c0; zr < c1; zr += 64) {
+            unsigned long long cov = 0ull;
 #pragma unroll
-        for (int k = 0; k < ZF_PLANES; ++k) p[k] = 0u;
-        int m = 0;
-        uint32_t at = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-            int maxb = 0, gv = 0, gb = 0, gdz = 0, k = 0;
-            for (int j = 0; j <= cnt; ++j) {
-                int v = 0, dz = 0, bb = 0;
-                if (j < cnt) {
-                    const uint32_t e = list[j * 256];
-                    v = (int)(e >> CL_Z_BITS);
-                    dz = z - (int)(e & CL_Z_MASK);
-                    bb = v - dz * dz;
-                }
-                if (v != gv) {                           // close the group of value gv
-                    if (gb > maxb) {
-                        const uint32_t w = zf_pack(gv, gdz);
-                        if (pass == 0) {
-#pragma unroll
-                            for (int q = 0; q < ZF_PLANES; ++q)
-                                if (q == k) p[q] = w;
-                        } else {
-                            region[at + k] = w;
-                        }
-                        ++k;
-                        maxb = gb;
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t e = h ? s1 : s0;
+                if (lane + 64 * h < cnt) {
+                    const int r = open_reach((int)(e >> CL_Z_BITS)), zc = (int)(e & CL_Z_MASK);
+                    const int a = max(zc - r, zr) - zr, b = min(zc + r, zr + 63) - zr;
+                    if (a <= b) {
+                        const int len = b - a + 1;
+                        cov |= (len == 64 ? ~0ull : ((1ull << len) - 1ull)) << a;
                     }
-                    if (v <= maxb) break;                // no residual below v can exceed maxb
-                    gv = v;
-                    gb = 0;
-                }
-                if (bb > gb) {
-                    gb = bb;
-                    gdz = dz;
                 }
             }
-            m = k;
-            if (pass == 1 || m <= ZF_PLANES) break;
-            at = atomicAdd(&s_used, (uint32_t)m);
-            if (at + (uint32_t)m > cap) break;           // region full: rescan instead
-        }
-        const size_t i = (size_t)z * plane + col;
-        if (m > ZF_PLANES) {
-            zf[i] = at + (uint32_t)m <= cap ? (7u << ZF_N_SHIFT) | ZF_SPILL | ((uint32_t)m << 16) | at
-                                            : 7u << ZF_N_SHIFT;
-            continue;
-        }
-        zf[i] = m ? (p[0] | ((uint32_t)m << ZF_N_SHIFT)) : 0u;
+            const uint32_t clo = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_or((uint32_t)cov), 63);
+            const uint32_t chi = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_or((uint32_t)(cov >> 32)), 63);
+            const int z = zr + lane;
+            const bool live = z < c1 && (((lane < 32 ? clo >> lane : chi >> (lane - 32)) & 1u) != 0u);
+            uint32_t p[ZF_PLANES];
 #pragma unroll
-        for (int q = 1; q < ZF_PLANES; ++q)
-            if (m > q) zf[q * n + i] = p[q];
+            for (int q = 0; q < ZF_PLANES; ++q) p[q] = 0u;
+            int m = 0;
+            uint32_t at = 0;
+            bool fits = false;
+            for (int pass = 0; pass < 2; ++pass) {
+                bool act = pass == 0 ? live : (m > ZF_PLANES && fits);
+                if (!__ballot(act)) break;
+                int maxb = 0, gv = 0, gb = 0, gdz = 0, k = 0;
+                for (int j = 0; j <= cnt; ++j) {
+                    const uint32_t e = j >= cnt ? 0u
+                                       : (uint32_t)__builtin_amdgcn_readlane((int)(j < 64 ? s0 : s1), j & 63);
+                    const int v = (int)(e >> CL_Z_BITS);
+                    const int dz = z - (int)(e & CL_Z_MASK);
+                    const int bb = v - __mul24(dz, dz);
+                    if (v != gv) {                    // wave-uniform: close the group of value gv
+                        if (act && gb > maxb) {
+                            const uint32_t w = zf_pack(gv, gdz);
+                            if (pass == 0) {
+#pragma unroll
+                                for (int q = 0; q < ZF_PLANES; ++q)
+                                    if (q == k) p[q] = w;
+                            } else {
+                                region[at + k] = w;
+                            }
+                            ++k;
+                            maxb = gb;
+                        }
+                        if (v <= maxb) act = false;   // no later residual can exceed maxb
+                        if (!__ballot(act)) break;
+                        gv = v;
+                        gb = 0;
+                    }
+                    if (act && bb > gb) {
+                        gb = bb;
+                        gdz = dz;
+                    }
+                }
+                if (pass == 1) break;
+                m = k;
+                if (m > ZF_PLANES) {
+                    at = atomicAdd(&s_used, (uint32_t)m);
+                    fits = at + (uint32_t)m <= cap;   // else: rescan instead
+                }
+            }
+            if (z < c1) {
+                uint32_t w0;
+                if (m > ZF_PLANES) {
+                    w0 = fits ? (7u << ZF_N_SHIFT) | ZF_SPILL | ((uint32_t)m << 16) | at : 7u << ZF_N_SHIFT;
+                } else {
+                    w0 = m ? (p[0] | ((uint32_t)m << ZF_N_SHIFT)) : 0u;
+                    const size_t i = (size_t)z * plane + col;
+#pragma unroll
+                    for (int q = 1; q < ZF_PLANES; ++q)
+                        if (m > q) zf[q * n + i] = p[q];
+                }
+                out[(z - zs) * FZ_STRIDE] = w0;
+            }
+        }
     }
+    __syncthreads();
+    for (int q = wid; q < c1 - c0; q += 4)
+        if (lane < W) zf[(size_t)(c0 + q) * plane + rowi + lane] = tile[(q + hb) * FZ_STRIDE + lane];
 }
 
 // ------------------------------------------------------------------ 2D pixel pass
@@ -521,47 +616,8 @@ __device__ __forceinline__ void paint_interval(const TileCtx& t, int row, int xs
     atomicMax(base + xe - (1 << k) + 1, v);
 }
 
-// Inclusive scans over the 64 lanes of a wave with DPP moves (VALU only, no LDS
-// traffic): row_shr by 1, 2, 4, 8 within each row of 16 lanes, then row_bcast:15
-// (rows 1 and 3 take the last lane of the row before) and row_bcast:31 (rows 2 and 3
-// take lane 31).  Lanes without a source take the identity.
-__device__ __forceinline__ int wave_scan_add(int x) {
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
-    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_scan_or(uint32_t x) {
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
-    return x;
-}
-
-__device__ __forceinline__ int wave_scan_max(int x) {                // identity -1
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
-    return x;
-}
-
 constexpr int DL_CAP = 128;          // discs per wave list
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Paint the n discs of the wave's list (all centred in source row sy).  Every
 // (disc, row) pair clipped to the tile is one interval; the pairs are spread over
@@ -842,9 +898,8 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                         const uint32_t* sp = spill;
                         if (spilled) {
                             m = (int)((e0 >> 16) & 0xffu);
-                            const size_t blk = ((size_t)(pz / chunk) * ((ny + 3) / 4) + sy / 4) * ((nx + 63) / 64) +
-                                               sx / 64;
-                            sp = spill + blk * (size_t)(SPILL_PER_SLICE * chunk) + (e0 & 0xffffu);
+                            const size_t blk = ((size_t)(pz / chunk) * ny + sy) * ((nx + 63) / 64) + sx / 64;
+                            sp = spill + blk * (size_t)(SPILL_ROW_SLICE * chunk) + (e0 & 0xffffu);
                         }
                         for (int q = 0; __ballot(q < m); ++q) {
                             const bool has = q < m;
@@ -978,10 +1033,10 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.counter = at; at += 256;
     o.zf = at;      at += align256((g.ndim == 3 ? ZF_PLANES : 1) * g.n * sizeof(uint32_t));
     o.kd = at;      at += g.ndim == 3 ? align256(g.n * sizeof(int32_t)) : 0;
-    // spill regions of the front pass: one per (64 x 4 column block, z chunk), sized
+    // spill regions of the front pass: one per (row of 64 columns, z chunk), sized
     // for the largest chunk (the z extent rounded up by at most 127 slices)
     o.spill = at;
-    at += g.ndim == 3 ? align256((size_t)((g.nx + 63) / 64) * ((g.ny + 3) / 4) * (g.nz + 127) * SPILL_PER_SLICE *
+    at += g.ndim == 3 ? align256((size_t)((g.nx + 63) / 64) * g.ny * (g.nz + 127) * SPILL_ROW_SLICE *
                                  sizeof(uint32_t))
                       : 0;
     o.colmax = at;  at += g.ndim == 3 ? align256((size_t)g.ny * g.nx * sizeof(int32_t)) : 0;
@@ -1054,7 +1109,6 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
                        s>>>(lab, g.nx, g.ny, g.nz, max_label, bb, nlab, ctx->d_err);
     }
     if (g.ndim == 3) {
-        const dim3 b2(64, 4);
         {
             ProfScope _p(ctx, s, "prune3d");
             prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + PR_TY - 1) / PR_TY, (g.nz + PR_ZB - 1) / PR_ZB),
@@ -1063,7 +1117,7 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         }
         {
             ProfScope _p(ctx, s, "fronts3d");
-            fronts3d<<<dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + chunk - 1) / chunk), b2, 0, s>>>(
+            fronts3d<<<dim3((g.nx + 63) / 64, g.ny, (g.nz + chunk - 1) / chunk), 256, fronts3d_lds(chunk), s>>>(
                 kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill);
         }
     } else {
