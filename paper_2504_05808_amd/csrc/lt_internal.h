@@ -203,9 +203,9 @@ constexpr double SUM_SCALE = 8388608.0;
 
 // floor(sqrt(n)) for 0 <= n < 2^30, exact: float estimate then one-step fix-ups.
 __device__ __forceinline__ int isqrt_floor(int n) {
-    int r = (int)__fsqrt_rn((float)n);
-    if (r * r > n) --r;
-    else if ((r + 1) * (r + 1) <= n) ++r;
+    int r = (int)__fsqrt_rn((float)n);                 // r < 2^15: 24-bit products are exact
+    if (__mul24(r, r) > n) --r;
+    else if (__mul24(r + 1, r + 1) <= n) ++r;
     return r;
 }
 

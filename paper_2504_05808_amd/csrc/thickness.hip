@@ -293,13 +293,15 @@ __device__ __forceinline__ uint32_t wave_scan_or(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ int wave_scan_max(int x) {                // identity -1
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
+// Inclusive maximum scan of non-negative values (identity 0, so each step folds into
+// one DPP max).
+__device__ __forceinline__ int wave_scan_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
     return x;
 }
 
@@ -611,7 +613,7 @@ __device__ __forceinline__ int reach_of(const TileCtx& t, int w) {
 // starting at xs and ending at xe, k = floor(log2(len)).
 __device__ __forceinline__ void paint_interval(const TileCtx& t, int row, int xs, int xe, uint32_t v) {
     const int k = 31 - __clz(xe - xs + 1);
-    uint32_t* base = t.M + k * t.lstride + row * TILE_STRIDE;
+    uint32_t* base = t.M + __mul24(k, t.lstride) + __mul24(row, TILE_STRIDE);
     atomicMax(base + xs, v);
     atomicMax(base + xe - (1 << k) + 1, v);
 }
@@ -698,7 +700,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
     }
     int carry = 0;
     for (int base = 0; base < total; base += 64) {
-        own[lane] = -1;
+        own[lane] = 0;                              // entry 0 is the smallest owner anyway
         wave_lds_sync();
 #pragma unroll
         for (int q = 0; q < 2; ++q)
@@ -714,7 +716,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
             const int dy = j + (xw >> 12) - 16384;
             int b, ro;
             disc_unpack<NDIM>(t, e_b[o], sy, b, ro);
-            const int hw = reach_of(t, b - dy * dy);
+            const int hw = reach_of(t, b - __mul24(dy, dy));
             const int xs = max(pxr - hw, 0);
             const int xe = min(pxr + hw, t.W - 1);
             if (xs <= xe) paint_interval(t, ro + dy, xs, xe, (uint32_t)e_v[o]);
