@@ -181,6 +181,50 @@ def test_large_objects_span_tiles(gpu):
     compare(run_gpu(gpu, lab3), ref3, lab3)
 
 
+def _lt_sq_at(lab, D, p, reach):
+    """LT^2 at voxel p from the definition: the largest D(c) over centres c of p's
+    label whose open ball |q - c|^2 < D(c) contains p."""
+    lo = [max(0, p[a] - reach) for a in range(3)]
+    hi = [min(lab.shape[a], p[a] + reach + 1) for a in range(3)]
+    sub = tuple(slice(lo[a], hi[a]) for a in range(3))
+    zz, yy, xx = np.meshgrid(*[np.arange(lo[a], hi[a]) for a in range(3)], indexing="ij")
+    d2 = (zz - p[0]) ** 2 + (yy - p[1]) ** 2 + (xx - p[2]) ** 2
+    ok = (lab[sub] == lab[p]) & (d2 < D[sub])
+    return int(D[sub][ok].max())
+
+
+def test_thick_cylinder_column_rescans(gpu):
+    """A cylinder of radius 34 along z (axis between voxels, end faces on the image
+    border): the central columns hold D = 1109 from slice 33 to Z - 34, and each of
+    those voxels is a kept centre (its neighbours' balls are no larger), so with reach
+    33 the 64-slice chunk [128, 192) of such a column lists 64 + 2 * 33 = 130 > 128
+    centres and the paint pass rescans the column there.  D is compared with the
+    oracle in full; LT at sampled voxels with its definition (the oracle's full LT
+    takes minutes here); volume, shell count and largest LT exactly."""
+    Z, Y, X, r = 264, 72, 72, 34
+    zz, yy, xx = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    lab = (((yy - 35.5) ** 2 + (xx - 35.5) ** 2) < r * r).astype(np.uint16)
+    _note(f"cylinder {lab.shape} r={r}")
+    got = run_gpu(gpu, lab)
+    D = O.edt_sq(lab).astype(np.int64)
+    np.testing.assert_array_equal(got["dist_sq"], D)
+    dmax = int(D.max())
+    reach = math.isqrt(dmax - 1)
+    assert dmax == 1109 and reach == 33
+    assert np.count_nonzero(D[128 - reach:192 + reach, 35, 35] == dmax) == 130
+    obj = np.argwhere(lab > 0)
+    rng = np.random.default_rng(11)
+    pick = obj[rng.choice(len(obj), 1500, replace=False)]
+    extra = [[z, 35, 35] for z in (0, 1, 33, 63, 64, 127, 128, 160, 191, 192, 230, 263)]
+    pick = np.concatenate([pick, extra, [[150, 35, 2], [150, 2, 35], [5, 35, 69]]])
+    want = np.array([_lt_sq_at(lab, D, tuple(p), reach) for p in pick])
+    np.testing.assert_array_equal(got["lt_sq"][tuple(pick.T)], want)
+    assert np.all(got["lt_sq"][lab == 0] == 0)
+    assert got["volume"][1] == int(lab.sum())
+    assert got["shell_count"][1] == int(O.shell_mask(lab).sum())
+    assert got["max_lt_sq"][1] == dmax
+
+
 def test_sparse_label_values_and_large_max_label(gpu):
     rng = synth.rng_for(77)
     lab = synth.random_labels(rng, (20, 30, 40), n_labels=4, blob=5, dtype=np.uint32)
