@@ -332,10 +332,10 @@ static size_t fronts3d_lds(int chunk) {
 // wave-uniformly with readlane, yields the Pareto front over (value D, residual
 // D - dz^2 > 0): by decreasing D, a group of equal D contributes its largest
 // residual when that exceeds every residual of larger D, and a lane stops at the
-// first D not above that maximum; slices no listed ball reaches take no part.  The
-// first ZF_PLANES members go to the planes (plane 0 back through the staging tile,
-// written out coalesced); a longer front is written whole to the block's spill
-// region (second scan).  A list longer than FZ_CAP, or a full spill region, marks
+// first D not above that maximum; slices no listed ball reaches take no part.  A
+// front of up to ZF_PLANES members goes to the planes (plane 0 back through the
+// staging tile, written out coalesced); a longer one is written whole to the
+// block's spill region (second scan).  A list longer than FZ_CAP, or a full spill region, marks
 // the fronts "rescan" (count 7 without ZF_SPILL): the paint pass then takes every
 // centre of the column (same result).
 __global__ void __launch_bounds__(256)
@@ -457,18 +457,21 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
                 if (!__ballot(act)) break;
                 int maxb = 0, gv = 0, gb = 0, gdz = 0, k = 0;
                 for (int j = 0; j <= cnt; ++j) {
-                    const uint32_t e = j >= cnt ? 0u
-                                       : (uint32_t)__builtin_amdgcn_readlane((int)(j < 64 ? s0 : s1), j & 63);
+                    uint32_t e = 0u;                  // wave-uniform list entry j (0 past the end)
+                    if (j < cnt) {
+                        if (j < 64) e = (uint32_t)__builtin_amdgcn_readlane((int)s0, j);
+                        else e = (uint32_t)__builtin_amdgcn_readlane((int)s1, j - 64);
+                    }
                     const int v = (int)(e >> CL_Z_BITS);
                     const int dz = z - (int)(e & CL_Z_MASK);
                     const int bb = v - __mul24(dz, dz);
                     if (v != gv) {                    // wave-uniform: close the group of value gv
                         if (act && gb > maxb) {
                             const uint32_t w = zf_pack(gv, gdz);
-                            if (pass == 0) {
+                            if (pass == 0) {                  // newest first; order is free
 #pragma unroll
-                                for (int q = 0; q < ZF_PLANES; ++q)
-                                    if (q == k) p[q] = w;
+                                for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = p[q - 1];
+                                p[0] = w;
                             } else {
                                 region[at + k] = w;
                             }
