@@ -22,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "rng_for", "haar_rotation", "ellipse_mask", "ellipsoid_mask", "ball_mask",
-    "superellipsoid_mask", "place_objects", "cfg1", "cfg2", "cfg3", "cfg4_volume",
+    "superellipsoid_mask", "place_objects", "cfg1", "cfg2", "cfg3", "cfg4_volume", "cfg4_batch",
     "cfg4_sizes", "random_labels", "single_object_crops", "CFG3_SHAPE",
 ]
 
@@ -378,6 +378,31 @@ def cfg4_volume(i: int, seed: int = 4, n_volumes: int = 64, edges=(96, 384), cou
     vol = np.zeros((edge, edge, edge), dtype=np.uint16)
     objs = _place_until(vol, rng, k, ("ellipsoid", "superellipsoid"))
     return vol, dict(name=f"cfg4[{i}]", objects=objs, n_objects=len(objs))
+
+
+def _cfg4_job(args):
+    i, kw = args
+    return i, cfg4_volume(i, **kw)[0]
+
+
+def cfg4_batch(seed: int = 4, n_volumes: int = 64, edges=(96, 384), counts=(10, 500),
+               workers: int | None = None):
+    """Every volume of the batched workload (``cfg4_volume`` for i = 0..n_volumes-1),
+    generated in parallel processes; returns the list in index order."""
+    kw = dict(seed=seed, n_volumes=n_volumes, edges=edges, counts=counts)
+    jobs = [(i, kw) for i in range(n_volumes)]
+    workers = workers or min(16, os.cpu_count() or 1)
+    vols = {}
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            for i, v in pool.imap_unordered(_cfg4_job, jobs):
+                vols[i] = v
+    else:
+        for j in jobs:
+            i, v = _cfg4_job(j)
+            vols[i] = v
+    return [vols[i] for i in range(n_volumes)]
 
 
 def _cfg5_block(args):

@@ -1,7 +1,8 @@
 """Batched form on the GPU: one captured graph over many volumes of uneven size
 gives bit-identical results to the plain per-volume calls, on every replay; the
 tuning knobs and the number of lanes change speed only; the autotuner caches its
-choice.  One batch volume is also checked against the CPU oracle."""
+choice.  One batch volume is also checked against the CPU oracle, and the full-size
+batch (64 cubes of edge 96-384) on sampled objects."""
 import json
 import os
 import sys
@@ -155,3 +156,50 @@ def test_autotune_and_cache(gpu, tmp_path):
         b.close()
     finally:
         ctx.set_tuning(**saved)
+
+
+def test_full_size_batch_sampled_objects(gpu):
+    """The full batched workload in one captured graph: 64 uint16 cubes with edges
+    U{96..384} and U{10..500} objects each (1.44e9 voxels).  Background is zero in
+    every volume; two sampled objects per volume, and the largest object of the
+    batch, are checked against the oracle on their crops: D and LT bit-exactly,
+    volume and largest LT exactly, the FP32 measures within 1e-5 of the FP64 forms.
+    The knobs do not change results (see test_batch_knobs_do_not_change_results), so
+    the default tuning stands in for the autotuned one."""
+    torch, lt = gpu
+    vols = synth.cfg4_batch()
+    print("full batch:", len(vols), "volumes,", sum(v.size for v in vols), "voxels", flush=True)
+    labs = [torch.from_numpy(v).cuda() for v in vols]
+    b = lt.Batch([(l, int(v.max())) for l, v in zip(labs, vols)])
+    b.run()
+    lt.default_context().sync_status()
+    rng = np.random.default_rng(8)
+    boxes = [O.object_boxes(v) for v in vols]
+    size = lambda bx: int(np.prod([h - lo for lo, h in zip(*bx)]))
+    ibig, lbig = max(((i, l) for i, bs in enumerate(boxes) for l in bs), key=lambda il: size(boxes[il[0]][il[1]]))
+    checked = 0
+    for i, v in enumerate(vols):
+        d, t, m = b.outputs[i]
+        D, LT = d.cpu().numpy(), t.cpu().numpy()
+        bg = v == 0
+        assert not D[bg].any() and not LT[bg].any(), f"volume {i}: background"
+        labels = sorted(boxes[i])
+        pick = set(int(x) for x in rng.choice(labels, min(2, len(labels)), replace=False)) if labels else set()
+        if i == ibig:
+            pick.add(int(lbig))
+        meas = {k: getattr(m, k).cpu().numpy() for k in KEYS}
+        for l in sorted(pick):
+            sl, msk, dref, ltref, _ = O._crop_fields(v, l, boxes[i][l])
+            np.testing.assert_array_equal(D[sl][msk], dref[msk], err_msg=f"D volume {i} label {l}")
+            np.testing.assert_array_equal(LT[sl][msk], ltref[msk], err_msg=f"LT volume {i} label {l}")
+            sums = O.object_sums(msk.astype(np.int32), np.where(msk, ltref, 0), 1)
+            cf = O.closed_forms(sums, 3)
+            assert meas["volume"][l] == sums["volume"][1] and meas["max_lt_sq"][l] == sums["max_lt_sq"][1]
+            assert meas["shell_count"][l] == sums["shell_count"][1]
+            for k in ("mean_lt", "shell_mean_lt", "sphericity", "roundness"):
+                assert meas[k][l] == pytest.approx(cf[k][1], rel=1e-5), (i, l, k)
+            checked += 1
+    print("objects checked:", checked, flush=True)
+    b.close()
+    del labs
+    torch.cuda.empty_cache()
