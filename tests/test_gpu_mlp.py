@@ -328,7 +328,8 @@ def test_learned_correction_on_1024_volume(gpu):
     whole GPU path measures every object, the network trained on the oracle-made
     set corrects the closed form, and the corrected sphericity is closer to the mesh
     sphericity (stored by a script that calls only the oracles) than the closed
-    form."""
+    form.  Sampled objects are also checked against the oracle (D and LT bit-exact,
+    measures within 1e-5)."""
     torch, lt = gpu
     if not os.path.exists(EVAL_TARGETS):
         pytest.skip("evaluation targets not generated")
@@ -341,8 +342,7 @@ def test_learned_correction_on_1024_volume(gpu):
     ml = int(meta["n_objects"])
     _note(f"volume ready: {ml} objects; running the path")
     t = torch.from_numpy(vol).cuda()
-    del vol
-    _, _, m = lt.measure(t, ml, hist=True)
+    d_sq, lt_sq, m = lt.measure(t, ml, hist=True)
     feats = lt.mlp_features(m)
     s_corr, nf = net.correct(feats, m.sphericity)
     lt.default_context().sync_status()
@@ -359,3 +359,26 @@ def test_learned_correction_on_1024_volume(gpu):
           f"corrected {e_net:.4f}, fallbacks {n_fb}")
     assert n_fb <= 0.02 * len(labels)
     assert e_net < 0.5 * e_cf
+    # the path itself at this size: D and LT of sampled objects (and the largest one)
+    # bit-exact on their crops, their measures within 1e-5 of the FP64 oracle
+    from scipy import ndimage
+    found = ndimage.find_objects(vol.view(np.int32))
+    boxes = {i + 1: (tuple(q.start for q in sl), tuple(q.stop for q in sl))
+             for i, sl in enumerate(found) if sl is not None}
+    rng = np.random.default_rng(12)
+    pick = set(int(x) for x in rng.choice(sorted(boxes), 40, replace=False))
+    pick.add(max(boxes, key=lambda l: np.prod([h - a for a, h in zip(*boxes[l])])))
+    meas = {k: getattr(m, k).cpu().numpy() for k in ("volume", "max_lt_sq", "shell_count", "mean_lt",
+                                                      "shell_mean_lt", "sphericity", "roundness")}
+    for l in sorted(pick):
+        sl, msk, dref, ltref, _ = O._crop_fields(vol, l, boxes[l])
+        tsl = tuple(slice(q.start, q.stop) for q in sl)
+        np.testing.assert_array_equal(d_sq[tsl].cpu().numpy()[msk], dref[msk], err_msg=f"D label {l}")
+        np.testing.assert_array_equal(lt_sq[tsl].cpu().numpy()[msk], ltref[msk], err_msg=f"LT label {l}")
+        sums = O.object_sums(msk.astype(np.int32), np.where(msk, ltref, 0), 1)
+        cf = O.closed_forms(sums, 3)
+        assert meas["volume"][l] == sums["volume"][1] and meas["max_lt_sq"][l] == sums["max_lt_sq"][1]
+        assert meas["shell_count"][l] == sums["shell_count"][1]
+        for k in ("mean_lt", "shell_mean_lt", "sphericity", "roundness"):
+            assert meas[k][l] == pytest.approx(cf[k][1], rel=1e-5), (l, k)
+    _note(f"1024^3: {len(pick)} sampled objects match the oracle")
