@@ -177,8 +177,9 @@ lt_status lt_batch_destroy(lt_batch* batch);
  * Runtime kernel knobs.  paint_tile_rows: 32 or 64 rows per local-thickness paint
  * tile (0 = 64 when the LDS allows); paint_blocks_per_cu: 1 or 2 persistent paint
  * blocks per compute unit (2 only takes effect with 32-row tiles); front_chunk: 32,
- * 64 or 128 slices per thread in the z-front pass; batch_lanes: 1..16 streams in a
- * batch graph.  Results never depend on the knobs, only the speed does. */
+ * 64 or 128 slices per block of the z-front pass (one lane per slice, 64 slices at
+ * a time); batch_lanes: 1..16 streams in a batch graph.  Results never depend on
+ * the knobs, only the speed does. */
 typedef struct {
     int paint_tile_rows;
     int paint_blocks_per_cu;

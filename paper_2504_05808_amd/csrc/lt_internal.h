@@ -67,7 +67,7 @@ struct Scratch {
 struct Tuning {
     int paint_tile_rows = 0;      // 32 or 64 rows per paint tile (0: 64 when LDS allows)
     int paint_blocks_per_cu = 1;  // persistent paint blocks per compute unit (1 or 2)
-    int front_chunk = 64;         // slices per thread in the z-front pass (32, 64 or 128)
+    int front_chunk = 64;         // slices per block of the z-front pass (32, 64 or 128)
     int batch_lanes = 4;          // concurrent streams in a captured batch graph
 };
 
