@@ -26,12 +26,13 @@ namespace lt {
 // consecutive slices of one row index y, so an object's runs meet in few blocks,
 // and the table is flushed to the global boxes once per block.
 constexpr int XBOX_TAB = 128;
+constexpr int XR = 4;                // slices per round of the x pass
 
 template <typename L, bool BOX>
 __global__ void __launch_bounds__(1024)
 edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, int nz, uint32_t* err,
            BoxTarget box, int zper) {
-    __shared__ unsigned long long s_start[ROW_MAX_CHUNKS], s_end[ROW_MAX_CHUNKS];
+    __shared__ unsigned long long s_start[XR][ROW_MAX_CHUNKS], s_end[XR][ROW_MAX_CHUNKS];
     __shared__ uint32_t s_key[BOX ? XBOX_TAB : 1];
     __shared__ int s_bb[6][BOX ? XBOX_TAB : 1];
     const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -47,77 +48,95 @@ edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, 
         __syncthreads();
     }
     const int zb = blockIdx.z * zper, ze = min(nz, zb + zper);
-  for (int z = zb; z < ze; ++z) {
-    const size_t row = (size_t)z * ny + y;
-    const L* r = lab + row * nx;
+  // XR slices per round: their loads are in flight together and they share the
+  // round's two barriers
+  for (int z0 = zb; z0 < ze; z0 += XR) {
     for (int c = wid; c < chunks; c += nw) {
         const int x = c * 64 + lane;
-        bool st = false, en = false;
-        if (x < nx) {
-            const L l = r[x];
-            if (label_negative(l)) atomicOr(err, ERR_LABEL);
-            st = x == 0 || r[x - 1] != l;
-            en = x == nx - 1 || r[x + 1] != l;
+        L lv[XR], lm[XR], lp[XR];
+#pragma unroll
+        for (int q = 0; q < XR; ++q) {
+            const bool ok = z0 + q < ze && x < nx;
+            const L* r = lab + ((size_t)(z0 + q) * ny + y) * nx;
+            lv[q] = ok ? r[x] : L(0);
+            lm[q] = ok && x > 0 ? r[x - 1] : L(0);
+            lp[q] = ok && x + 1 < nx ? r[x + 1] : L(0);
         }
-        const unsigned long long ms = __ballot(st), me = __ballot(en);
-        if (lane == 0) {
-            s_start[c] = ms;
-            s_end[c] = me;
+#pragma unroll
+        for (int q = 0; q < XR; ++q) {
+            const bool ok = z0 + q < ze && x < nx;
+            bool st = false, en = false;
+            if (ok) {
+                if (label_negative(lv[q])) atomicOr(err, ERR_LABEL);
+                st = x == 0 || lm[q] != lv[q];
+                en = x == nx - 1 || lp[q] != lv[q];
+            }
+            const unsigned long long ms = __ballot(st), me = __ballot(en);
+            if (lane == 0) {
+                s_start[q][c] = ms;
+                s_end[q][c] = me;
+            }
         }
     }
     __syncthreads();
     for (int c = wid; c < chunks; c += nw) {
         const int x = c * 64 + lane;
         if (x >= nx) continue;
-        const L l = r[x];
-        int out = 0;
-        if (l != 0) {
-            const unsigned long long below = s_start[c] & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-            int s0;
-            if (below) {
-                s0 = c * 64 + 63 - __clzll(below);
-            } else {
-                int cc = c - 1;
-                while (s_start[cc] == 0ull) --cc;          // chunk 0 always has a start at x = 0
-                s0 = cc * 64 + 63 - __clzll(s_start[cc]);
-            }
-            const unsigned long long above = s_end[c] & ~((1ull << lane) - 1ull);
-            int e0;
-            if (above) {
-                e0 = c * 64 + __ffsll(above) - 1;
-            } else {
-                int cc = c + 1;
-                while (s_end[cc] == 0ull) ++cc;            // the last chunk ends at x = nx - 1
-                e0 = cc * 64 + __ffsll(s_end[cc]) - 1;
-            }
-            out = min(x - s0 + 1, e0 - x + 1);
-            if (BOX && x == s0) {                          // first voxel of its run
-                if ((uint64_t)l > box.max_label) {
-                    atomicOr(err, ERR_LABEL);
-                } else if (!label_negative(l)) {
-                    const uint32_t u = (uint32_t)l;
-                    const int slot = lds_slot<XBOX_TAB>(s_key, u);
-                    if (slot >= 0) {
-                        atomicMin(&s_bb[0][slot], z);
-                        atomicMax(&s_bb[1][slot], z);
-                        atomicMin(&s_bb[2][slot], y);
-                        atomicMax(&s_bb[3][slot], y);
-                        atomicMin(&s_bb[4][slot], s0);
-                        atomicMax(&s_bb[5][slot], e0);
-                    } else {
-                        atomicMin(&box.bb[0 * box.nlab + u], z);
-                        atomicMax(&box.bb[1 * box.nlab + u], z);
-                        atomicMin(&box.bb[2 * box.nlab + u], y);
-                        atomicMax(&box.bb[3 * box.nlab + u], y);
-                        atomicMin(&box.bb[4 * box.nlab + u], s0);
-                        atomicMax(&box.bb[5 * box.nlab + u], e0);
+#pragma unroll
+        for (int q = 0; q < XR; ++q) {
+            const int z = z0 + q;
+            if (z >= ze) break;
+            const size_t row = (size_t)z * ny + y;
+            const L l = lab[row * nx + x];
+            int out = 0;
+            if (l != 0) {
+                const unsigned long long below = s_start[q][c] & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+                int s0;
+                if (below) {
+                    s0 = c * 64 + 63 - __clzll(below);
+                } else {
+                    int cc = c - 1;
+                    while (s_start[q][cc] == 0ull) --cc;       // chunk 0 always has a start at x = 0
+                    s0 = cc * 64 + 63 - __clzll(s_start[q][cc]);
+                }
+                const unsigned long long above = s_end[q][c] & ~((1ull << lane) - 1ull);
+                int e0;
+                if (above) {
+                    e0 = c * 64 + __ffsll(above) - 1;
+                } else {
+                    int cc = c + 1;
+                    while (s_end[q][cc] == 0ull) ++cc;         // the last chunk ends at x = nx - 1
+                    e0 = cc * 64 + __ffsll(s_end[q][cc]) - 1;
+                }
+                out = min(x - s0 + 1, e0 - x + 1);
+                if (BOX && x == s0) {                          // first voxel of its run
+                    if ((uint64_t)l > box.max_label) {
+                        atomicOr(err, ERR_LABEL);
+                    } else if (!label_negative(l)) {
+                        const uint32_t u = (uint32_t)l;
+                        const int slot = lds_slot<XBOX_TAB>(s_key, u);
+                        if (slot >= 0) {
+                            atomicMin(&s_bb[0][slot], z);
+                            atomicMax(&s_bb[1][slot], z);
+                            atomicMin(&s_bb[2][slot], y);
+                            atomicMax(&s_bb[3][slot], y);
+                            atomicMin(&s_bb[4][slot], s0);
+                            atomicMax(&s_bb[5][slot], e0);
+                        } else {
+                            atomicMin(&box.bb[0 * box.nlab + u], z);
+                            atomicMax(&box.bb[1 * box.nlab + u], z);
+                            atomicMin(&box.bb[2 * box.nlab + u], y);
+                            atomicMax(&box.bb[3 * box.nlab + u], y);
+                            atomicMin(&box.bb[4 * box.nlab + u], s0);
+                            atomicMax(&box.bb[5 * box.nlab + u], e0);
+                        }
                     }
                 }
             }
+            g[row * nx + x] = (uint16_t)out;
         }
-        g[row * nx + x] = (uint16_t)out;
     }
-    __syncthreads();                                     // the masks are reused by the next row
+    __syncthreads();                                     // the masks are reused by the next round
   }
     if (BOX) {
         for (int t = threadIdx.x; t < XBOX_TAB; t += blockDim.x) {
