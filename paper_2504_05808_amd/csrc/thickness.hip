@@ -222,6 +222,9 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
             keep = true;
             if (d <= PRUNE_DCAP) {
                 const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d], a3 = tab[2 * (PRUNE_DCAP + 1) + d];
+                // largest D over the face, edge and corner neighbours: the centre is
+                // dropped when one class exceeds its table value
+                int m1 = 0, m2 = 0, m3 = 0;
 #pragma unroll
                 for (int dz = -1; dz <= 1; ++dz) {
                     const int sl = (z + dz + 3) % 3;
@@ -232,9 +235,12 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
                             const int k = dz * dz + dy * dy + dx * dx;
                             if (k == 0) continue;
                             const int dn = s_d[sl][ty + 1 + dy][tx + 1 + dx];
-                            keep = keep && !(dn > (k == 1 ? a1 : (k == 2 ? a2 : a3)));
+                            if (k == 1) m1 = max(m1, dn);
+                            else if (k == 2) m2 = max(m2, dn);
+                            else m3 = max(m3, dn);
                         }
                 }
+                keep = m1 <= a1 && m2 <= a2 && m3 <= a3;
             }
             if (keep && d > (int)ZF_D_MASK) atomicOr(err, ERR_OVERFLOW);
             if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;   // flagged elsewhere
@@ -535,6 +541,7 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
         keep = true;
         if (d <= PRUNE_DCAP) {
             const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d];
+            int m1 = 0, m2 = 0;                          // largest D of the edge / corner neighbours
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
@@ -543,8 +550,10 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
                     if (k == 0) continue;
                     const bool inb = y + dy >= 0 && y + dy < ny && x + dx >= 0 && x + dx < nx;
                     const int dn = inb ? D[(ptrdiff_t)i + (ptrdiff_t)dy * nx + dx] : 0;
-                    keep = keep && !(dn > (k == 1 ? a1 : a2));
+                    if (k == 1) m1 = max(m1, dn);
+                    else m2 = max(m2, dn);
                 }
+            keep = m1 <= a1 && m2 <= a2;
         }
         zf[i] = keep ? ((uint32_t)d | 0x80000000u) : 0u;
         if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;
