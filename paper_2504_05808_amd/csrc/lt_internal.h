@@ -199,6 +199,21 @@ inline int loop_extent(int n_outer, long other_blocks, const lt_ctx* ctx, int pe
 // Fixed-point scale of the deterministic radius sums (Q.23 in uint64).
 constexpr double SUM_SCALE = 8388608.0;
 
+// round(sqrt(v) * 2^23) for 0 <= v < 2^24, the per-voxel term of the radius sums
+// (every kernel that forms it calls this, so the fused and separate sums agree bit
+// for bit).  sqrt starts from the FP32 reciprocal square root (relative error about
+// 2^-23) and takes two FP64 corrections y += (v - y^2) * h with h = rsq / 2: the
+// error falls to about 2^-46, then below 2^-60, well inside an FP64 ulp.
+__device__ __forceinline__ uint64_t radius_q23(int v) {
+    const double x = (double)v;
+    const float rf = __builtin_amdgcn_rsqf((float)(v > 0 ? v : 1));
+    const double h = 0.5 * (double)rf;
+    double y = x * (double)rf;
+    y = fma(fma(-y, y, x), h, y);
+    y = fma(fma(-y, y, x), h, y);
+    return v > 0 ? (uint64_t)(y * SUM_SCALE + 0.5) : 0ull;
+}
+
 // ---------------------------------------------------------------- device helpers
 
 // floor(sqrt(n)) for 0 <= n < 2^30, exact: float estimate then one-step fix-ups.

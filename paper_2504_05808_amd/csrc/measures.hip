@@ -96,7 +96,7 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
                 } else {
                     l = (uint32_t)raw;
                     v = lt[i];
-                    q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
+                    q = radius_q23(v);
                     shell = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 ||
                             lab[i - 1] != raw || lab[i + 1] != raw || lab[i - nx] != raw ||
                             lab[i + nx] != raw;

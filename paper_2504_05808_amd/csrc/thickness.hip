@@ -782,6 +782,16 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     // the wave that reads it out.
     for (int q = tid; q < TILE_LEVELS * (tile_y * TILE_STRIDE + 1); q += blockDim.x) M[q] = 0u;
     for (int w = tid; w < REACH_TAB; w += blockDim.x) s_reach[w] = (uint8_t)(w > 0 ? open_reach(w) : 0);
+    // push-down shifts: level k reads lane - 2^(k-1) (byte index for ds_bpermute),
+    // masked to zero on the lanes below that offset
+    uint32_t pd_idx[TILE_LEVELS], pd_sel[TILE_LEVELS];
+#pragma unroll
+    for (int k = 1; k < TILE_LEVELS; ++k) {
+        const int half = 1 << (k - 1);
+        pd_idx[k] = (uint32_t)((lane - half) & 63) << 2;
+        pd_sel[k] = lane >= half ? ~0u : 0u;
+    }
+    pd_idx[0] = pd_sel[0] = 0u;
     for (;;) {
         if (tid == 0) {
             s_item = atomicAdd(counter, 1u);
@@ -970,13 +980,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                 for (int k = 0; k < TILE_LEVELS; ++k)
                     val[k] = (k < nlev && lane < t.W) ? t.M[k * t.lstride + row * TILE_STRIDE + lane] : 0u;
 #pragma unroll
-                for (int k = TILE_LEVELS - 1; k >= 1; --k) {
-                    if (k < nlev) {
-                        const int half = 1 << (k - 1);
-                        const uint32_t up = __shfl_up(val[k], (unsigned)half, 64);
-                        const uint32_t vk = lane >= half ? max(val[k], up) : val[k];
-                        val[k - 1] = max(val[k - 1], vk);
-                    }
+                for (int k = TILE_LEVELS - 1; k >= 1; --k) {          // levels >= nlev hold zeros
+                    const uint32_t up =
+                        (uint32_t)__builtin_amdgcn_ds_bpermute((int)pd_idx[k], (int)val[k]) & pd_sel[k];
+                    val[k - 1] = max(val[k - 1], max(val[k], up));
                 }
                 if (lane < t.W) {
                     if (val[0]) {
@@ -985,7 +992,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                         lt[gi] = (int32_t)val[0];
                         if (ms.vol) {
                             const int v = (int)val[0];
-                            const uint64_t q = (uint64_t)(sqrt((double)v) * SUM_SCALE + 0.5);
+                            const uint64_t q = radius_q23(v);
                             // on the shell exactly when a face neighbour (or the image
                             // border) is not of the object: D = 1
                             const bool shell = Dmap[gi] == 1;
