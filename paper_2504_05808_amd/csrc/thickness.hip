@@ -826,7 +826,6 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         t.lstride = t.H * TILE_STRIDE + 1;
         const int sy0 = max(y0, t.ty0 - R), sy1 = min(y1, t.ty0 + t.H + R);
         const int sx0 = max(x0, t.tx0 - R), sx1 = min(x1, t.tx0 + t.W + R);
-        const int nlev = 32 - __clz(min(t.W, 2 * R + 1));   // levels 0 .. floor(log2(span))
         // fused measures: this thread's share of the item's volume, radius sums,
         // largest LT and shell terms (every painted cell is a voxel of label l)
         uint32_t a_n = 0, a_sn = 0;
@@ -975,12 +974,15 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             if (tid == 0) s_dirty[(pz + 1) & 1] = 0ull;   // the next slice's mask
             for (int row = wid; row < t.H; row += nwaves) {
                 if (!((painted >> row) & 1ull)) continue;
+                // levels above floor(log2(min(W, 2R + 1))) are never painted and hold
+                // zeros: every level is read and cleared, so the lane mask is the only
+                // condition
                 uint32_t val[TILE_LEVELS];
 #pragma unroll
                 for (int k = 0; k < TILE_LEVELS; ++k)
-                    val[k] = (k < nlev && lane < t.W) ? t.M[k * t.lstride + row * TILE_STRIDE + lane] : 0u;
+                    val[k] = lane < t.W ? t.M[k * t.lstride + row * TILE_STRIDE + lane] : 0u;
 #pragma unroll
-                for (int k = TILE_LEVELS - 1; k >= 1; --k) {          // levels >= nlev hold zeros
+                for (int k = TILE_LEVELS - 1; k >= 1; --k) {
                     const uint32_t up =
                         (uint32_t)__builtin_amdgcn_ds_bpermute((int)pd_idx[k], (int)val[k]) & pd_sel[k];
                     val[k - 1] = max(val[k - 1], max(val[k], up));
@@ -1006,8 +1008,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                         }
                     }
 #pragma unroll
-                    for (int k = 0; k < TILE_LEVELS; ++k)
-                        if (k < nlev) t.M[k * t.lstride + row * TILE_STRIDE + lane] = 0u;
+                    for (int k = 0; k < TILE_LEVELS; ++k) t.M[k * t.lstride + row * TILE_STRIDE + lane] = 0u;
                 }
             }
             __syncthreads();
