@@ -782,16 +782,15 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     // the wave that reads it out.
     for (int q = tid; q < TILE_LEVELS * (tile_y * TILE_STRIDE + 1); q += blockDim.x) M[q] = 0u;
     for (int w = tid; w < REACH_TAB; w += blockDim.x) s_reach[w] = (uint8_t)(w > 0 ? open_reach(w) : 0);
-    // push-down shifts: level k reads lane - 2^(k-1) (byte index for ds_bpermute),
-    // masked to zero on the lanes below that offset
-    uint32_t pd_idx[TILE_LEVELS], pd_sel[TILE_LEVELS];
+    // push-down shifts: level k reads lane - 2^(k-1) (byte index for ds_bpermute);
+    // the lanes below that offset read themselves, which leaves their maximum as it is
+    uint32_t pd_idx[TILE_LEVELS];
 #pragma unroll
     for (int k = 1; k < TILE_LEVELS; ++k) {
         const int half = 1 << (k - 1);
-        pd_idx[k] = (uint32_t)((lane - half) & 63) << 2;
-        pd_sel[k] = lane >= half ? ~0u : 0u;
+        pd_idx[k] = (uint32_t)(lane >= half ? lane - half : lane) << 2;
     }
-    pd_idx[0] = pd_sel[0] = 0u;
+    pd_idx[0] = 0u;
     for (;;) {
         if (tid == 0) {
             s_item = atomicAdd(counter, 1u);
@@ -983,8 +982,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     val[k] = lane < t.W ? t.M[k * t.lstride + row * TILE_STRIDE + lane] : 0u;
 #pragma unroll
                 for (int k = TILE_LEVELS - 1; k >= 1; --k) {
-                    const uint32_t up =
-                        (uint32_t)__builtin_amdgcn_ds_bpermute((int)pd_idx[k], (int)val[k]) & pd_sel[k];
+                    const uint32_t up = (uint32_t)__builtin_amdgcn_ds_bpermute((int)pd_idx[k], (int)val[k]);
                     val[k - 1] = max(val[k - 1], max(val[k], up));
                 }
                 if (lane < t.W) {
