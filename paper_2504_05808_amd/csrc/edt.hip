@@ -183,7 +183,8 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
     // bits), then the value with its bits; the values wait in registers meanwhile
     __shared__ uint32_t s_val[LINE_ROWS * 64];
     constexpr int RPT = LINE_ROWS / 8;                     // staged rows per thread
-    const int tx = threadIdx.x, ty = threadIdx.y;          // 64 x 8
+    const int tx = threadIdx.x;                            // 64 x 8: one wave per ty
+    const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int x = blockIdx.x * 64 + tx;
     const int n = AXIS == 1 ? ny : nz;
     const int a0 = (AXIS == 1 ? blockIdx.y : blockIdx.z) * LINE_T;

@@ -71,7 +71,8 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
     __shared__ uint32_t s_key[SUM_TAB];
     __shared__ unsigned long long s_vol[SUM_TAB], s_shc[SUM_TAB], s_sq[SUM_TAB], s_ssq[SUM_TAB];
     __shared__ int s_mx[SUM_TAB];
-    const int tid = threadIdx.y * 64 + threadIdx.x;
+    const int wy = __builtin_amdgcn_readfirstlane((int)threadIdx.y);   // one wave per row of the brick
+    const int tid = wy * 64 + threadIdx.x;
     if (tid < SUM_TAB) {
         s_key[tid] = 0u;
         s_vol[tid] = s_shc[tid] = s_sq[tid] = s_ssq[tid] = 0ull;
@@ -79,7 +80,7 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
     }
     __syncthreads();
     const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * SUM_BY + threadIdx.y;
+    const int y = blockIdx.y * SUM_BY + wy;
     const size_t plane = (size_t)ny * nx;
     const int z0 = blockIdx.z * SUM_BZ, z1 = min(nz, z0 + SUM_BZ);
     for (int z = z0; z < z1; ++z) {

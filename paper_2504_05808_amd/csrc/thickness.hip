@@ -169,7 +169,8 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     __shared__ int32_t s_d[3][PR_H][PR_W];
     __shared__ uint32_t s_key[PR_TAB];
     __shared__ int s_max[PR_TAB];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+    const int tx = threadIdx.x;                                   // 64 x PR_TY: one wave per ty
+    const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y), tid = ty * 64 + tx;
     const int x0 = blockIdx.x * 64, y0 = blockIdx.y * PR_TY;
     const int x = x0 + tx, y = y0 + ty;
     const bool inside = x < nx && y < ny;
