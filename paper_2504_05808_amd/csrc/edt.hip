@@ -173,7 +173,9 @@ constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LI
 // Value a staged word offers a search walking down (up) to it: its value, or 0 when
 // the word carries the boundary bit of that direction (a site of another label).
 __device__ __forceinline__ int line_down(uint32_t w) { return (int)(w & LINE_VAL) & ~((int)w >> 31); }
-__device__ __forceinline__ int line_up(uint32_t w) { return (int)(w & LINE_VAL) & ~((int)(w << 1) >> 31); }
+__device__ __forceinline__ int line_up(uint32_t w) {    // w << 1: the up bit becomes the sign
+    return (int)((uint32_t)max((int)(w << 1), 0) >> 1);
+}
 
 template <typename L, int AXIS, typename F>
 __global__ void __launch_bounds__(512)
