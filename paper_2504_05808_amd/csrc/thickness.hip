@@ -155,9 +155,11 @@ __device__ __forceinline__ void wave_label_max(uint32_t l, bool valid, int d, in
 
 
 // One thread per voxel: background LT = 0; a centre is kept unless a 26-neighbour's
-// open ball contains its ball; kd = D for kept centres, 0 elsewhere; per-label max
-// of the kept D (the global max follows in max_over_labels).
+// open ball contains its ball; kd = D for kept centres, 0 elsewhere, stored
+// column-major ([y][x][z], each column's slices contiguous) for the z-front pass;
+// per-label max of the kept D.
 constexpr int PR_TY = 8, PR_ZB = 16, PR_W = 66, PR_H = PR_TY + 2, PR_TAB = 64;
+constexpr int PR_KS = PR_TY * 64 + 1;    // slice stride of the block's kept-field buffer (odd: no bank conflicts)
 
 template <typename L>
 __global__ void __launch_bounds__(512)
@@ -167,6 +169,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     // a block walks PR_ZB consecutive slices of a 64 x PR_TY tile; D of the slices
     // below, at and above the current one (tile + 1 voxel halo) rotate through LDS
     __shared__ int32_t s_d[3][PR_H][PR_W];
+    __shared__ int32_t s_kd[PR_ZB * PR_KS];             // kept field of the block, [z][y][x]
     __shared__ uint32_t s_key[PR_TAB];
     __shared__ int s_max[PR_TAB];
     const int tx = threadIdx.x;                                   // 64 x PR_TY: one wave per ty
@@ -247,10 +250,8 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
             if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;   // flagged elsewhere
             l = (uint32_t)raw;
         }
-        if (inside) {
-            kd[i] = keep ? d : 0;
-            if (d <= 0) lt[i] = 0;
-        }
+        s_kd[(z - zs) * PR_KS + ty * 64 + tx] = keep ? d : 0;
+        if (inside && d <= 0) lt[i] = 0;
         if (keep) cmax = max(cmax, d);
         // per-label largest kept D: wave maxima merged in the block table
         uint64_t active = __ballot(keep);
@@ -272,6 +273,17 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     }
     if (tid < PR_TAB && s_key[tid] != 0u) atomicMax(&maxd[s_key[tid]], s_max[tid]);
     if (cmax > 0) atomicMax(&colmax[(size_t)y * nx + x], cmax);
+    // the kept field goes out column-major ([y][x][z]): 16 lanes write one column's
+    // PR_ZB slices as one contiguous run
+#pragma unroll
+    for (int it = 0; it < PR_ZB; ++it) {
+        const int idx = it * 512 + tid;
+        const int c = idx / PR_ZB, zo = idx % PR_ZB;     // column of the tile, slice offset
+        const int cy = c >> 6, cx = c & 63;
+        const int gx = x0 + cx, gy = y0 + cy, gz = zs + zo;
+        if (gx < nx && gy < ny && gz < ze)
+            kd[((size_t)gy * nx + gx) * nz + gz] = s_kd[zo * PR_KS + cy * 64 + cx];
+    }
 }
 
 // ------------------------------------------------------------------ wave helpers
@@ -320,28 +332,26 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ------------------------------------------------------------------ 3D z-fronts
 
-constexpr int FZ_H = 32;            // staged slices on each side of the chunk
 constexpr int FZ_CAP = 128;         // listed centres per column (two per lane)
 constexpr int FZ_LIST = FZ_CAP + 4; // list words per wave (zero padding for 4-wide reads)
-constexpr int FZ_STRIDE = 65;       // staging-tile row stride in words (conflict-free columns)
+constexpr int FZ_STRIDE = 65;       // output-tile row stride in words (conflict-free columns)
 
 static size_t fronts3d_lds(int chunk) {
-    return (size_t)(4 * 2 * FZ_LIST + (chunk + 2 * FZ_H) * FZ_STRIDE) * sizeof(uint32_t);
+    return (size_t)(4 * 2 * FZ_LIST + chunk * FZ_STRIDE) * sizeof(uint32_t);
 }
 
-// One block per (row y, 64 columns, chunk of `chunk` slices), four waves.  The
-// kept-centre field of the block's columns over the chunk +- the largest column
-// reach (at most FZ_H) is staged in LDS with coalesced row loads.  Each wave then
-// takes whole columns, lanes along z: the column's kept centres within the chunk
-// grown by the column's own reach R are compacted (ballots) into the wave's list,
+// One block per (row y, 64 columns, chunk of `chunk` slices), four waves.  Each
+// wave takes whole columns, lanes along z: the column's kept centres within the
+// chunk grown by the column's own reach R, read straight from the column-major kept
+// field (contiguous along z), are compacted (ballots) into the wave's list,
 // ordered by D (each entry's rank counted against the whole list), and held two per
 // lane in registers.  For each slice (one per lane) a scan of the list, read
 // wave-uniformly with readlane, yields the Pareto front over (value D, residual
 // D - dz^2 > 0): by decreasing D, a group of equal D contributes its largest
 // residual when that exceeds every residual of larger D, and a lane stops at the
 // first D not above that maximum; slices no listed ball reaches take no part.  A
-// front of up to ZF_PLANES members goes to the planes (plane 0 back through the
-// staging tile, written out coalesced); a longer one is written whole to the
+// front of up to ZF_PLANES members goes to the planes (plane 0 through an LDS tile,
+// written out coalesced along x); a longer one is written whole to the
 // block's spill region (second scan).  A list longer than FZ_CAP, or a full spill region, marks
 // the fronts "rescan" (count 7 without ZF_SPILL): the paint pass then takes every
 // centre of the column (same result).
@@ -350,7 +360,6 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
     extern __shared__ __align__(16) uint32_t S[];
     __shared__ int s_cm[64];
-    __shared__ int s_hb;
     __shared__ uint32_t s_used;                       // words of the block's spill region in use
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);    // wave-uniform, in a scalar register
@@ -361,33 +370,12 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     const size_t n = plane * nz;
     const size_t rowi = (size_t)y * nx + x0;          // column of lane 0
     if (wid == 0) {
-        const int cm = lane < W ? colmax[rowi + lane] : 0;
-        s_cm[lane] = cm;
-        int r = cm > 0 ? open_reach(cm) : 0;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) r = max(r, __shfl_xor(r, off, 64));
-        if (lane == 0) {
-            s_hb = min(r, FZ_H);
-            s_used = 0u;
-        }
+        s_cm[lane] = lane < W ? colmax[rowi + lane] : 0;
+        if (lane == 0) s_used = 0u;
     }
     __syncthreads();
-    const int hb = s_hb;
-    const int zs = c0 - hb;                           // first staged slice (may be < 0)
-    const int rows = (c1 - c0) + 2 * hb;
+    const int zs = c0;                                // first slice of the output tile
     uint32_t* tile = S + 4 * 2 * FZ_LIST;
-    for (int q0 = wid; q0 < rows; q0 += 32) {         // eight rows in flight per wave
-        uint32_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = q0 + 4 * u, z = zs + q;
-            v[u] = (q < rows && z >= 0 && z < nz && lane < W) ? (uint32_t)kd[(size_t)z * plane + rowi + lane] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (q0 + 4 * u < rows) tile[(q0 + 4 * u) * FZ_STRIDE + lane] = v[u];
-    }
-    __syncthreads();
     uint32_t* list = S + wid * 2 * FZ_LIST;           // compacted, then sorted
     uint32_t* sorted = list + FZ_LIST;
     const uint32_t cap = (uint32_t)(SPILL_ROW_SLICE * chunk);
@@ -404,10 +392,10 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
         const int R = open_reach(cm);                 // no ball of the column reaches farther
         const int lo = max(0, c0 - R), hi = min(nz, c1 + R);
         int cnt = 0;
+        const int32_t* kcol = kd + col * (size_t)nz;  // the column's kept field (column-major)
         for (int zb = lo; zb < hi; zb += 64) {
             const int z = zb + lane;
-            int v = 0;
-            if (z < hi) v = (z >= zs && z < zs + rows) ? (int)out[(z - zs) * FZ_STRIDE] : kd[(size_t)z * plane + col];
+            const int v = z < hi ? kcol[z] : 0;
             const unsigned long long m = __ballot(v > 0);
             if (v > 0) {
                 const int pos = cnt + __popcll(m & below);
@@ -519,7 +507,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     }
     __syncthreads();
     for (int q = wid; q < c1 - c0; q += 4)
-        if (lane < W) zf[(size_t)(c0 + q) * plane + rowi + lane] = tile[(q + hb) * FZ_STRIDE + lane];
+        if (lane < W) zf[(size_t)(c0 + q) * plane + rowi + lane] = tile[q * FZ_STRIDE + lane];
 }
 
 // ------------------------------------------------------------------ 2D pixel pass
@@ -942,13 +930,12 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     // together, four independent loads at a time.
                     if (NDIM == 3 && __ballot(rescan)) {
                         const size_t col = (size_t)sy * nx + sx;
-                        const size_t pl = (size_t)nx * ny;
                         for (int d0 = -R; d0 <= R; d0 += 4) {
                             int kv[4];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int zc = pz + d0 + u;
-                                kv[u] = (rescan && d0 + u <= R && zc >= z0 && zc < z1) ? kd[(size_t)zc * pl + col] : 0;
+                                kv[u] = (rescan && d0 + u <= R && zc >= z0 && zc < z1) ? kd[col * (size_t)nz + zc] : 0;
                             }
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
