@@ -158,11 +158,12 @@ __device__ __forceinline__ void wave_label_max(uint32_t l, bool valid, int d, in
 // open ball contains its ball; kd = D for kept centres, 0 elsewhere, stored
 // column-major ([y][x][z], each column's slices contiguous) for the z-front pass;
 // per-label max of the kept D.
-constexpr int PR_TY = 8, PR_ZB = 16, PR_W = 66, PR_H = PR_TY + 2, PR_TAB = 64;
+constexpr int PR_TY = 4, PR_ZB = 16, PR_W = 66, PR_H = PR_TY + 2, PR_TAB = 64;
+constexpr int PR_NT = PR_TY * 64;        // threads per block
 constexpr int PR_KS = PR_TY * 64 + 1;    // slice stride of the block's kept-field buffer (odd: no bank conflicts)
 
 template <typename L>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(PR_NT)
 prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny, int nz,
         uint32_t max_label, const int32_t* __restrict__ tab, int32_t* __restrict__ kd,
         int32_t* __restrict__ lt, int32_t* __restrict__ maxd, int32_t* __restrict__ colmax, uint32_t* err) {
@@ -186,11 +187,12 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     // each thread moves (at most) two words of a halo plane: loaded into registers
     // one slice ahead, stored to LDS at the top of the next iteration
     constexpr int PR_N = PR_H * PR_W;
+    static_assert(2 * PR_NT >= PR_N, "two words per thread cover a halo plane");
     int pv[2];
     auto fetch = [&](int z) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int q = tid + u * 512;
+            const int q = tid + u * PR_NT;
             const int hy = q / PR_W, hx = q - hy * PR_W;
             const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
             pv[u] = (q < PR_N && z >= 0 && z < nz && gy >= 0 && gy < ny && gx >= 0 && gx < nx)
@@ -202,7 +204,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         const int slot = (z + 3) % 3;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int q = tid + u * 512;
+            const int q = tid + u * PR_NT;
             if (q < PR_N) (&s_d[slot][0][0])[q] = pv[u];
         }
     };
@@ -277,7 +279,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
     // PR_ZB slices as one contiguous run
 #pragma unroll
     for (int it = 0; it < PR_ZB; ++it) {
-        const int idx = it * 512 + tid;
+        const int idx = it * PR_NT + tid;
         const int c = idx / PR_ZB, zo = idx % PR_ZB;     // column of the tile, slice offset
         const int cy = c >> 6, cx = c & 63;
         const int gx = x0 + cx, gy = y0 + cy, gz = zs + zo;
