@@ -342,6 +342,47 @@ static size_t fronts3d_lds(int chunk) {
     return (size_t)(4 * 2 * FZ_LIST + chunk * FZ_STRIDE) * sizeof(uint32_t);
 }
 
+// Pareto front of one column's list (s0, s1: entries lane and lane + 64, sorted by
+// decreasing (D << 11) | zc) at slice z of each lane.  An entry (v, zc) is taken
+// when its residual b = v - (z - zc)^2 exceeds maxb, the largest residual taken so
+// far (INT_MAX: a lane that takes no part), and goes to the front at once: a larger
+// residual of the same D as the lane's last member replaces that member (a group
+// of equal D contributes only its largest residual; of equal residuals the first,
+// the larger zc, stays), any other is appended.  The wave stops once no lane has
+// maxb below the current D.  Members go to p, newest first, or with SPILL to
+// out[0..k).  Returns the front length k.
+template <bool SPILL>
+__device__ __forceinline__ int front_scan(uint32_t s0, uint32_t s1, int cnt, int z, int maxb,
+                                          uint32_t (&p)[ZF_PLANES], uint32_t* out) {
+    int k = 0, lastv = 0;                 // front length, D of the last member
+    bool more = true;                     // wave-uniform: a lane with maxb < D
+    auto step = [&](uint32_t e) {         // one wave-uniform list entry
+        const int v = (int)(e >> CL_Z_BITS);
+        const int dz = z - (int)(e & CL_Z_MASK);
+        const int b = v - __mul24(dz, dz);
+        const bool em = b > maxb;
+        if (__ballot(em)) {               // selects over the whole wave
+            const bool app = em && lastv != v;
+            const uint32_t w = zf_pack(v, dz);
+            if (SPILL) {
+                if (em) out[app ? k : k - 1] = w;
+            } else {
+#pragma unroll
+                for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = app ? p[q - 1] : p[q];
+                p[0] = em ? w : p[0];
+            }
+            k += app ? 1 : 0;
+            lastv = em ? v : lastv;
+            maxb = em ? b : maxb;
+        }
+        more = __ballot(maxb < v) != 0ull;
+    };
+    const int n0 = min(cnt, 64);
+    for (int j = 0; more && j < n0; ++j) step((uint32_t)__builtin_amdgcn_readlane((int)s0, j));
+    for (int j = 64; more && j < cnt; ++j) step((uint32_t)__builtin_amdgcn_readlane((int)s1, j - 64));
+    return k;
+}
+
 // One block per (row y, 64 columns, chunk of `chunk` slices), four waves.  Each
 // wave takes whole columns, lanes along z: the column's kept centres within the
 // chunk grown by the column's own reach R, read straight from the column-major kept
@@ -395,15 +436,22 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
         const int lo = max(0, c0 - R), hi = min(nz, c1 + R);
         int cnt = 0;
         const int32_t* kcol = kd + col * (size_t)nz;  // the column's kept field (column-major)
-        for (int zb = lo; zb < hi; zb += 64) {
-            const int z = zb + lane;
-            const int v = z < hi ? kcol[z] : 0;
-            const unsigned long long m = __ballot(v > 0);
-            if (v > 0) {
-                const int pos = cnt + __popcll(m & below);
-                if (pos < FZ_CAP) list[pos] = ((uint32_t)v << CL_Z_BITS) | (uint32_t)z;
+        for (int zb = lo; zb < hi; zb += 128) {      // two loads in flight per round
+            int v[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int z = zb + 64 * u + lane;
+                v[u] = z < hi ? kcol[z] : 0;
             }
-            cnt += __popcll(m);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const unsigned long long m = __ballot(v[u] > 0);
+                if (v[u] > 0) {
+                    const int pos = cnt + __popcll(m & below);
+                    if (pos < FZ_CAP) list[pos] = ((uint32_t)v[u] << CL_Z_BITS) | (uint32_t)(zb + 64 * u + lane);
+                }
+                cnt += __popcll(m);
+            }
         }
         if (cnt > FZ_CAP) {
             for (int z = c0 + lane; z < c1; z += 64) out[(z - zs) * FZ_STRIDE] = 7u << ZF_N_SHIFT;
@@ -449,48 +497,14 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             int m = 0;
             uint32_t at = 0;
             bool fits = false;
-            for (int pass = 0; pass < 2; ++pass) {
-                bool act = pass == 0 ? live : (m > ZF_PLANES && fits);
-                if (!__ballot(act)) break;
-                int maxb = 0, gv = 0, gb = 0, gdz = 0, k = 0;
-                for (int j = 0; j <= cnt; ++j) {
-                    uint32_t e = 0u;                  // wave-uniform list entry j (0 past the end)
-                    if (j < cnt) {
-                        if (j < 64) e = (uint32_t)__builtin_amdgcn_readlane((int)s0, j);
-                        else e = (uint32_t)__builtin_amdgcn_readlane((int)s1, j - 64);
-                    }
-                    const int v = (int)(e >> CL_Z_BITS);
-                    const int dz = z - (int)(e & CL_Z_MASK);
-                    const int bb = v - __mul24(dz, dz);
-                    if (v != gv) {                    // wave-uniform: close the group of value gv
-                        if (act && gb > maxb) {
-                            const uint32_t w = zf_pack(gv, gdz);
-                            if (pass == 0) {                  // newest first; order is free
-#pragma unroll
-                                for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = p[q - 1];
-                                p[0] = w;
-                            } else {
-                                region[at + k] = w;
-                            }
-                            ++k;
-                            maxb = gb;
-                        }
-                        if (v <= maxb) act = false;   // no later residual can exceed maxb
-                        if (!__ballot(act)) break;
-                        gv = v;
-                        gb = 0;
-                    }
-                    if (act && bb > gb) {
-                        gb = bb;
-                        gdz = dz;
-                    }
-                }
-                if (pass == 1) break;
-                m = k;
+            if (__ballot(live)) {
+                m = front_scan<false>(s0, s1, cnt, z, live ? 0 : INT_MAX, p, nullptr);
                 if (m > ZF_PLANES) {
                     at = atomicAdd(&s_used, (uint32_t)m);
                     fits = at + (uint32_t)m <= cap;   // else: rescan instead
                 }
+                const bool again = m > ZF_PLANES && fits;   // second scan: the whole front to the spill
+                if (__ballot(again)) front_scan<true>(s0, s1, cnt, z, again ? 0 : INT_MAX, p, region + at);
             }
             if (z < c1) {
                 uint32_t w0;
