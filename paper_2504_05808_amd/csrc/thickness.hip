@@ -337,49 +337,63 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int FZ_CAP = 128;         // listed centres per column (two per lane)
 constexpr int FZ_LIST = FZ_CAP + 4; // list words per wave (zero padding for 4-wide reads)
 constexpr int FZ_STRIDE = 65;       // output-tile row stride in words (conflict-free columns)
+constexpr int FZ_WAVE = 2 * FZ_LIST + FZ_CAP / 4;   // LDS words per wave: list / pairs, D of every fourth
 
 static size_t fronts3d_lds(int chunk) {
-    return (size_t)(4 * 2 * FZ_LIST + chunk * FZ_STRIDE) * sizeof(uint32_t);
+    return (size_t)(4 * FZ_WAVE + chunk * FZ_STRIDE) * sizeof(uint32_t);
 }
 
-// Pareto front of one column's list (s0, s1: entries lane and lane + 64, sorted by
-// decreasing (D << 11) | zc) at slice z of each lane.  An entry (v, zc) is taken
-// when its residual b = v - (z - zc)^2 exceeds maxb, the largest residual taken so
-// far (INT_MAX: a lane that takes no part), and goes to the front at once: a larger
-// residual of the same D as the lane's last member replaces that member (a group
-// of equal D contributes only its largest residual; of equal residuals the first,
-// the larger zc, stays), any other is appended.  The wave stops once no lane has
-// maxb below the current D.  Members go to p, newest first, or with SPILL to
-// out[0..k).  Returns the front length k.
+// Pareto front of one column's list at slice z of each lane.  ent holds the entries
+// as (zc, A = v - zc^2) by decreasing (D << 11) | zc, padded to cnt4 (a multiple of
+// four) with entries no slice takes.  An entry (v, zc) is taken when its residual
+// b = v - (z - zc)^2 exceeds maxb, the largest residual taken so far: with
+// t = b + z^2 = A + 2 z zc (one 24-bit multiply-add) and the lane's threshold
+// mz = maxb + z^2 (INT_MAX: a lane that takes no part) the test is t > mz.  A taken
+// entry goes to the front at once: a larger residual of the same D as the lane's
+// last member replaces that member (a group of equal D contributes only its largest
+// residual; of equal residuals the first, the larger zc, stays), any other is
+// appended.  Entries come four at a time (LDS broadcasts); four that no lane takes
+// cost one test.  dq[i] holds the D of entry
+// 4 i + 3; the wave stops once no lane has maxb below it.  Members go to p, newest first, or with
+// SPILL to out[0..k).  Returns the front length k.
 template <bool SPILL>
-__device__ __forceinline__ int front_scan(uint32_t s0, uint32_t s1, int cnt, int z, int maxb,
+__device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int cnt4, int z, bool act,
                                           uint32_t (&p)[ZF_PLANES], uint32_t* out) {
+    const int z2 = 2 * z, zsq = __mul24(z, z);
+    int mz = act ? zsq : INT_MAX;
     int k = 0, lastv = 0;                 // front length, D of the last member
     bool more = true;                     // wave-uniform: a lane with maxb < D
-    auto step = [&](uint32_t e) {         // one wave-uniform list entry
-        const int v = (int)(e >> CL_Z_BITS);
-        const int dz = z - (int)(e & CL_Z_MASK);
-        const int b = v - __mul24(dz, dz);
-        const bool em = b > maxb;
-        if (__ballot(em)) {               // selects over the whole wave
-            const bool app = em && lastv != v;
-            const uint32_t w = zf_pack(v, dz);
-            if (SPILL) {
-                if (em) out[app ? k : k - 1] = w;
-            } else {
+    for (int j = 0; more && j < cnt4; j += 4) {
+        const uint4 qa = ent[j >> 1], qb = ent[(j >> 1) + 1];
+        const int d4 = dq[j >> 2];
+        const int zc[4] = {(int)qa.x, (int)qa.z, (int)qb.x, (int)qb.z};
+        const int A[4] = {(int)qa.y, (int)qa.w, (int)qb.y, (int)qb.w};
+        int t[4];
 #pragma unroll
-                for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = app ? p[q - 1] : p[q];
-                p[0] = em ? w : p[0];
+        for (int u = 0; u < 4; ++u) t[u] = __mul24(z2, zc[u]) + A[u];
+        if (__ballot(max(max(t[0], t[1]), max(t[2], t[3])) > mz)) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool em = t[u] > mz;
+                if (__ballot(em)) {       // selects over the whole wave
+                    const int v = zc[u] * zc[u] + A[u];
+                    const bool app = em && lastv != v;
+                    const uint32_t w = zf_pack(v, z - zc[u]);
+                    if (SPILL) {
+                        if (em) out[app ? k : k - 1] = w;
+                    } else {
+#pragma unroll
+                        for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = app ? p[q - 1] : p[q];
+                        p[0] = em ? w : p[0];
+                    }
+                    k += app ? 1 : 0;
+                    lastv = em ? v : lastv;
+                    mz = em ? t[u] : mz;
+                }
             }
-            k += app ? 1 : 0;
-            lastv = em ? v : lastv;
-            maxb = em ? b : maxb;
         }
-        more = __ballot(maxb < v) != 0ull;
-    };
-    const int n0 = min(cnt, 64);
-    for (int j = 0; more && j < n0; ++j) step((uint32_t)__builtin_amdgcn_readlane((int)s0, j));
-    for (int j = 64; more && j < cnt; ++j) step((uint32_t)__builtin_amdgcn_readlane((int)s1, j - 64));
+        more = __ballot(mz < d4 + zsq) != 0ull;   // maxb below the D of the fourth
+    }
     return k;
 }
 
@@ -418,9 +432,9 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     }
     __syncthreads();
     const int zs = c0;                                // first slice of the output tile
-    uint32_t* tile = S + 4 * 2 * FZ_LIST;
-    uint32_t* list = S + wid * 2 * FZ_LIST;           // compacted, then sorted
-    uint32_t* sorted = list + FZ_LIST;
+    uint32_t* tile = S + 4 * FZ_WAVE;
+    uint32_t* list = S + wid * FZ_WAVE;               // compacted keys, then ranked pairs
+    int* dq = (int*)(list + 2 * FZ_LIST);             // D of the entries 3, 7, 11, ... by rank
     const uint32_t cap = (uint32_t)(SPILL_ROW_SLICE * chunk);
     uint32_t* region = spill + ((size_t)blockIdx.z * ny + y) * gridDim.x * (size_t)cap + (size_t)blockIdx.x * cap;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -468,16 +482,31 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             r0 += (q.x > e0) + (q.y > e0) + (q.z > e0) + (q.w > e0);
             r1 += (q.x > e1) + (q.y > e1) + (q.z > e1) + (q.w > e1);
         }
-        if (lane < cnt) sorted[r0] = e0;
-        if (lane + 64 < cnt) sorted[r1] = e1;
+        // the list area now takes the entries by rank as (zc, v - zc^2), padded to a
+        // multiple of four with entries no slice takes
+        const int cnt4 = (cnt + 3) & ~3;
+        uint2* ent = (uint2*)list;
+        wave_lds_sync();                              // every lane has read the keys
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t e = h ? e1 : e0;
+            const int r = h ? r1 : r0, zc = (int)(e & CL_Z_MASK), v = (int)(e >> CL_Z_BITS);
+            if (lane + 64 * h < cnt) {
+                ent[r] = make_uint2((uint32_t)zc, (uint32_t)(v - zc * zc));
+                if ((r & 3) == 3) dq[r >> 2] = v;
+            }
+        }
+        if (lane < cnt4 - cnt) {                      // padding: never taken, ends the scan
+            ent[cnt + lane] = make_uint2(0u, 0xc0000000u);
+            if (((cnt + lane) & 3) == 3) dq[(cnt + lane) >> 2] = INT_MIN / 2;
+        }
         wave_lds_sync();
-        const uint32_t s0 = sorted[lane], s1 = sorted[lane + 64];   // entries lane, lane + 64
         // slices each listed ball reaches, per 64-slice round
         for (int zr = c0; zr < c1; zr += 64) {
             unsigned long long cov = 0ull;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const uint32_t e = h ? s1 : s0;
+                const uint32_t e = h ? e1 : e0;       // order is free here
                 if (lane + 64 * h < cnt) {
                     const int r = open_reach((int)(e >> CL_Z_BITS)), zc = (int)(e & CL_Z_MASK);
                     const int a = max(zc - r, zr) - zr, b = min(zc + r, zr + 63) - zr;
@@ -498,13 +527,13 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             uint32_t at = 0;
             bool fits = false;
             if (__ballot(live)) {
-                m = front_scan<false>(s0, s1, cnt, z, live ? 0 : INT_MAX, p, nullptr);
+                m = front_scan<false>((const uint4*)ent, dq, cnt4, z, live, p, nullptr);
                 if (m > ZF_PLANES) {
                     at = atomicAdd(&s_used, (uint32_t)m);
                     fits = at + (uint32_t)m <= cap;   // else: rescan instead
                 }
                 const bool again = m > ZF_PLANES && fits;   // second scan: the whole front to the spill
-                if (__ballot(again)) front_scan<true>(s0, s1, cnt, z, again ? 0 : INT_MAX, p, region + at);
+                if (__ballot(again)) front_scan<true>((const uint4*)ent, dq, cnt4, z, again, p, region + at);
             }
             if (z < c1) {
                 uint32_t w0;
