@@ -400,18 +400,17 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
 // One block per (row y, 64 columns, chunk of `chunk` slices), four waves.  Each
 // wave takes whole columns, lanes along z: the column's kept centres within the
 // chunk grown by the column's own reach R, read straight from the column-major kept
-// field (contiguous along z), are compacted (ballots) into the wave's list,
-// ordered by D (each entry's rank counted against the whole list), and held two per
-// lane in registers.  For each slice (one per lane) a scan of the list, read
-// wave-uniformly with readlane, yields the Pareto front over (value D, residual
-// D - dz^2 > 0): by decreasing D, a group of equal D contributes its largest
-// residual when that exceeds every residual of larger D, and a lane stops at the
-// first D not above that maximum; slices no listed ball reaches take no part.  A
-// front of up to ZF_PLANES members goes to the planes (plane 0 through an LDS tile,
-// written out coalesced along x); a longer one is written whole to the
-// block's spill region (second scan).  A list longer than FZ_CAP, or a full spill region, marks
-// the fronts "rescan" (count 7 without ZF_SPILL): the paint pass then takes every
-// centre of the column (same result).
+// field (contiguous along z), are compacted (ballots) into the wave's list when
+// their ball reaches a slice of the chunk, ranked by D (each entry's rank counted
+// against the whole list) and stored by rank as (zc, D - zc^2) pairs.  For each
+// slice (one per lane) a scan of the pairs (front_scan) yields the Pareto front over
+// (value D, residual D - dz^2 > 0): by decreasing D, a group of equal D contributes
+// its largest residual when that exceeds every residual of larger D; slices no
+// listed ball reaches take no part.  A front of up to ZF_PLANES members goes to the
+// planes (plane 0 through an LDS tile, written out coalesced along x); a longer one
+// is written whole to the block's spill region (second scan).  A list longer than
+// FZ_CAP, or a full spill region, marks the fronts "rescan" (count 7 without
+// ZF_SPILL): the paint pass then takes every centre of the column (same result).
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
@@ -459,10 +458,14 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const unsigned long long m = __ballot(v[u] > 0);
-                if (v[u] > 0) {
+                // a centre listed only when its ball reaches a slice of the chunk
+                const int z = zb + 64 * u + lane;
+                const int d = max(max(c0 - z, z - (c1 - 1)), 0);
+                const bool keep = v[u] > __mul24(d, d);
+                const unsigned long long m = __ballot(keep);
+                if (keep) {
                     const int pos = cnt + __popcll(m & below);
-                    if (pos < FZ_CAP) list[pos] = ((uint32_t)v[u] << CL_Z_BITS) | (uint32_t)(zb + 64 * u + lane);
+                    if (pos < FZ_CAP) list[pos] = ((uint32_t)v[u] << CL_Z_BITS) | (uint32_t)z;
                 }
                 cnt += __popcll(m);
             }
