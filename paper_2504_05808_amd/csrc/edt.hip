@@ -228,18 +228,16 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         if (p >= n) break;
         const size_t i = base + (size_t)p * stride + x;
         const uint32_t w0 = s_val[r * 64 + tx];
-        int best = (int)(w0 & LINE_VAL);
-        if (best == 0) {                                   // background (object values are >= 1)
-            out[i] = 0;
-            continue;
-        }
+        int best = (int)(w0 & LINE_VAL);                   // 0: background, no search
         // A position past a label boundary offers k^2 (its run ends there); once that
         // happens best <= k^2 and every later candidate, at least (k + 1)^2, loses, so
         // the search needs no per-direction stop: it ends when k^2 reaches best.
         int k = 1;
         // staged range, four steps per round: the eight words are loaded first so
-        // that their latencies overlap; the steps are then applied in order
-        while (k * k < best && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
+        // that their latencies overlap; the steps are then applied in order.  The
+        // wave runs while any lane still searches (a lane already done only takes
+        // candidates that cannot lower its best), so the loop needs no exec masks.
+        while (__ballot(k * k < best) != 0ull && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
             uint32_t wl[4], wh[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -254,7 +252,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             }
             k += 4;
         }
-        for (; k * k < best; ++k) {
+        for (; __ballot(k * k < best) != 0ull; ++k) {
             if (r - k < 0 || r + k >= LINE_ROWS) break;           // leave the staged range
             const uint32_t wl = s_val[(r - k) * 64 + tx], wh = s_val[(r + k) * 64 + tx];
             best = min(best, k * k + min(line_down(wl), line_up(wh)));
