@@ -166,7 +166,10 @@ __global__ void init_boxes(int32_t* bb, uint32_t nlab) {
 // the next position stops there), LINE_BLK_UP when it differs from the previous
 // one's; positions outside the image count as background.  Each voxel's outward
 // search then reads one LDS word per step and direction.  A search that runs past
-// the staged range continues with global loads (exact either way).
+// the staged range continues with global loads (exact either way).  The y pass
+// stages its 11-bit input g in both direction forms instead: the low half holds g,
+// or 0 below a run end (LINE_BLK_DN), the high half g, or 0 past a run start
+// (LINE_BLK_UP), so a step's candidate is a 24-bit square of one half.
 constexpr int LINE_T = 64, LINE_H = 32, LINE_ROWS = LINE_T + 2 * LINE_H;
 constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LINE_BLK_UP - 1u;
 
@@ -175,6 +178,16 @@ constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LI
 __device__ __forceinline__ int line_down(uint32_t w) { return (int)(w & LINE_VAL) & ~((int)w >> 31); }
 __device__ __forceinline__ int line_up(uint32_t w) {    // w << 1: the up bit becomes the sign
     return (int)((uint32_t)max((int)(w << 1), 0) >> 1);
+}
+
+// Smaller of the values offered by the word wl below and wh above the searching position.
+template <int AXIS>
+__device__ __forceinline__ int line_pair(uint32_t wl, uint32_t wh) {
+    if (AXIS == 1) {
+        const int a = (int)(wl & 0xffffu), b = (int)(wh >> 16);
+        return min(__mul24(a, a), __mul24(b, b));
+    }
+    return min(line_down(wl), line_up(wh));
 }
 
 template <typename L, int AXIS, typename F>
@@ -195,6 +208,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
     const size_t base = AXIS == 1 ? (size_t)o * ny * nx : (size_t)o * nx;   // (a = 0, x = 0)
     const int lo = max(0, a0 - LINE_H), hi = min(n, a0 + LINE_T + LINE_H);
     uint32_t vals[RPT];
+    uint32_t obj = 0u;                                     // y pass: bit q, staged row ty + 8q holds g >= 1
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int r = ty + 8 * q;
@@ -207,7 +221,8 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             fv = (int)f[i];
         }
         s_val[r * 64 + tx] = (uint32_t)lv;
-        vals[q] = (uint32_t)(AXIS == 1 ? fv * fv : fv);
+        vals[q] = (uint32_t)fv;
+        if (AXIS == 1 && fv > 0) obj |= 1u << q;
     }
     __syncthreads();
 #pragma unroll
@@ -216,7 +231,10 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         const uint32_t lv = s_val[r * 64 + tx];
         const bool dn = r + 1 >= LINE_ROWS || s_val[(r + 1) * 64 + tx] != lv;
         const bool up = r == 0 || s_val[(r - 1) * 64 + tx] != lv;
-        vals[q] |= (dn ? LINE_BLK_DN : 0u) | (up ? LINE_BLK_UP : 0u);
+        if (AXIS == 1)
+            vals[q] = (dn ? 0u : vals[q]) | ((up ? 0u : vals[q]) << 16);
+        else
+            vals[q] |= (dn ? LINE_BLK_DN : 0u) | (up ? LINE_BLK_UP : 0u);
     }
     __syncthreads();
 #pragma unroll
@@ -228,7 +246,14 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         if (p >= n) break;
         const size_t i = base + (size_t)p * stride + x;
         const uint32_t w0 = s_val[r * 64 + tx];
-        int best = (int)(w0 & LINE_VAL);                   // 0: background, no search
+        int best;                                          // 0: background, no search
+        if (AXIS == 1) {
+            // g from either half; a run of one position (both halves 0) has D2 = 1
+            const int g0 = (int)max(w0 & 0xffffu, w0 >> 16);
+            best = g0 ? __mul24(g0, g0) : (int)((obj >> ((r - ty) >> 3)) & 1u);
+        } else {
+            best = (int)(w0 & LINE_VAL);
+        }
         // A position past a label boundary offers k^2 (its run ends there); once that
         // happens best <= k^2 and every later candidate, at least (k + 1)^2, loses, so
         // the search needs no per-direction stop: it ends when k^2 reaches best.
@@ -247,7 +272,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             int kk = k * k;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                best = min(best, kk + min(line_down(wl[u]), line_up(wh[u])));
+                best = min(best, kk + line_pair<AXIS>(wl[u], wh[u]));
                 kk += 2 * (k + u) + 1;
             }
             k += 4;
@@ -255,7 +280,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         for (; __ballot(k * k < best) != 0ull; ++k) {
             if (r - k < 0 || r + k >= LINE_ROWS) break;           // leave the staged range
             const uint32_t wl = s_val[(r - k) * 64 + tx], wh = s_val[(r + k) * 64 + tx];
-            best = min(best, k * k + min(line_down(wl), line_up(wh)));
+            best = min(best, k * k + line_pair<AXIS>(wl, wh));
         }
         const L l = k * k < best ? lab[i] : L(0);
         for (; k * k < best; ++k) {                                // beyond the halo
