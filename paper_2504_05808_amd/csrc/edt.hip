@@ -26,7 +26,7 @@ namespace lt {
 // consecutive slices of one row index y, so an object's runs meet in few blocks,
 // and the table is flushed to the global boxes once per block.
 constexpr int XBOX_TAB = 128;
-constexpr int XR = 4;                // slices per round of the x pass
+constexpr int XR = 8;                // slices per round of the x pass
 
 template <typename L, bool BOX>
 __global__ void __launch_bounds__(1024)
