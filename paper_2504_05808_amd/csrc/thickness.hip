@@ -135,6 +135,50 @@ __device__ __forceinline__ uint32_t zf_pack(int v, int dz) {
     return (uint32_t)v | ((uint32_t)(dz + 512) << ZF_DZ_SHIFT);
 }
 
+// ------------------------------------------------------------------ wave helpers
+
+// Inclusive scans over the 64 lanes of a wave with DPP moves (VALU only, no LDS
+// traffic): row_shr by 1, 2, 4, 8 within each row of 16 lanes, then row_bcast:15
+// (rows 1 and 3 take the last lane of the row before) and row_bcast:31 (rows 2 and 3
+// take lane 31).  Lanes without a source take the identity.
+__device__ __forceinline__ int wave_scan_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_scan_or(uint32_t x) {
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    return x;
+}
+
+// Inclusive maximum scan of non-negative values (identity 0, so each step folds into
+// one DPP max).
+__device__ __forceinline__ int wave_scan_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ 3D centre prune
 
 // Running maximum of D per label: the lanes of a wave holding the same label fold
@@ -143,11 +187,9 @@ __device__ __forceinline__ void wave_label_max(uint32_t l, bool valid, int d, in
     uint64_t active = __ballot(valid);
     while (active) {
         const int lead = __ffsll((unsigned long long)active) - 1;
-        const uint32_t L0 = (uint32_t)__shfl((int)l, lead, 64);
+        const uint32_t L0 = (uint32_t)__builtin_amdgcn_readlane((int)l, lead);
         const bool in = valid && l == L0;
-        int m = in ? d : 0;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+        const int m = __builtin_amdgcn_readlane(wave_scan_max(in ? d : 0), 63);
         if ((int)(threadIdx.x & 63) == lead) atomicMax(&maxd[L0], m);
         active &= ~__ballot(in);
     }
@@ -259,11 +301,9 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         uint64_t active = __ballot(keep);
         while (active) {
             const int lead = __ffsll((unsigned long long)active) - 1;
-            const uint32_t L0 = (uint32_t)__shfl((int)l, lead, 64);
+            const uint32_t L0 = (uint32_t)__builtin_amdgcn_readlane((int)l, lead);
             const bool in = keep && l == L0;
-            int m = in ? d : 0;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+            const int m = __builtin_amdgcn_readlane(wave_scan_max(in ? d : 0), 63);
             if (tx == lead) {
                 const int slot = lds_slot<PR_TAB>(s_key, L0);
                 if (slot >= 0) atomicMax(&s_max[slot], m);
@@ -286,50 +326,6 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         if (gx < nx && gy < ny && gz < ze)
             kd[((size_t)gy * nx + gx) * nz + gz] = s_kd[zo * PR_KS + cy * 64 + cx];
     }
-}
-
-// ------------------------------------------------------------------ wave helpers
-
-// Inclusive scans over the 64 lanes of a wave with DPP moves (VALU only, no LDS
-// traffic): row_shr by 1, 2, 4, 8 within each row of 16 lanes, then row_bcast:15
-// (rows 1 and 3 take the last lane of the row before) and row_bcast:31 (rows 2 and 3
-// take lane 31).  Lanes without a source take the identity.
-__device__ __forceinline__ int wave_scan_add(int x) {
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
-    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_scan_or(uint32_t x) {
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
-    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
-    return x;
-}
-
-// Inclusive maximum scan of non-negative values (identity 0, so each step folds into
-// one DPP max).
-__device__ __forceinline__ int wave_scan_max(int x) {
-    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
-    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
-    return x;
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ------------------------------------------------------------------ 3D z-fronts
