@@ -20,17 +20,37 @@
 
 namespace lt {
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-    unsigned long long w = (unsigned long long)v;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) w += __shfl_xor(w, off, 64);
-    return (uint64_t)w;
+// Wave totals by inclusive DPP scans (row_shr 1, 2, 4, 8 within rows of 16 lanes,
+// then row_bcast:15 and row_bcast:31; lanes without a source take the identity 0),
+// read from lane 63: VALU only, no LDS permutes.  Every lane of the wave must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_add_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xf, false);
+    return v + (((uint64_t)hi << 32) | lo);
 }
 
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    v = dpp_add_u64<0x111, 0xf>(v);       // row_shr:1
+    v = dpp_add_u64<0x112, 0xf>(v);       // row_shr:2
+    v = dpp_add_u64<0x114, 0xf>(v);       // row_shr:4
+    v = dpp_add_u64<0x118, 0xf>(v);       // row_shr:8
+    v = dpp_add_u64<0x142, 0xa>(v);       // row_bcast:15
+    v = dpp_add_u64<0x143, 0xc>(v);       // row_bcast:31
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Wave maximum of non-negative values (identity 0).
 __device__ __forceinline__ int wave_max_i32(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return v;
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __global__ void zero_measure_arrays(uint64_t* vol, uint64_t* shc, int32_t* mx, uint64_t* sq,
@@ -109,7 +129,7 @@ object_sums(const L* __restrict__ lab, const int32_t* __restrict__ lt, int nx, i
         uint64_t active = __ballot(l != 0);
         while (active) {
             const int lead = __ffsll((unsigned long long)active) - 1;
-            const uint32_t L0 = (uint32_t)__shfl((int)l, lead, 64);
+            const uint32_t L0 = (uint32_t)__builtin_amdgcn_readlane((int)l, lead);
             const bool in = (l == L0);
             const uint64_t m = __ballot(in);
             const uint64_t sm = __ballot(in && shell);
