@@ -8,6 +8,9 @@ the closed-form sphericity S_LT, and the mesh sphericity S_mesh from the
 marching-tetrahedra iso-surface.  Record i draws from seed 5_000_000 + i.
 
 usage: python tests/golden/make_mlp_set.py N OUT.npz [workers]
+
+If OUT.npz already holds the first M < N records, only records M..N-1 are computed
+and appended (record i depends on i alone, so the result equals a fresh run).
 """
 from __future__ import annotations
 
@@ -67,14 +70,26 @@ def main():
     workers = int(sys.argv[3]) if len(sys.argv) > 3 else os.cpu_count() or 1
     t0 = time.time()
     shard = 2000
-    parts = []
+    parts = _load(out) if os.path.exists(out) else []
+    if len(parts) >= n:
+        print(f"{out} already holds {len(parts)} records", flush=True)
+        return
     with Pool(workers) as pool:
-        for s0 in range(0, n, shard):
+        for s0 in range(len(parts), n, shard):
             recs = pool.map(record, range(s0, min(n, s0 + shard)), chunksize=8)
             parts.extend(recs)
             print(f"{len(parts)}/{n} records, {time.time() - t0:.0f}s", flush=True)
             if len(parts) % 20000 == 0 or len(parts) == n:
                 _save(out, parts)
+
+
+def _load(out):
+    d = np.load(out)
+    if int(d["seed0"]) != SEED0:
+        raise ValueError(f"{out} was written with another seed base")
+    feat = np.concatenate([d["hist"].astype(np.float32), d["extra"]], axis=1)
+    return [(feat[i], float(d["s_lt"][i]), float(d["s_mesh"][i]), float(d["volume"][i]), int(d["kind"][i]))
+            for i in range(len(feat))]
 
 
 def _save(out, parts):

@@ -132,3 +132,23 @@ def test_ellipsoid_mesh_area_against_exact_area():
         ratio = M.iso_area(m) / _ellipsoid_area(*axes)
         assert 1.18 < ratio < 1.30, (axes, ratio)
         assert M.iso_volume(m) == pytest.approx(m.sum(), rel=0.01)
+
+
+def test_mesh_sphericity_single_voxels_hand_value():
+    """One voxel: the 0.5 iso-surface is made of one triangle in each of the 24
+    tetrahedra of the cube split around it, spanned by the midpoints of its three
+    edges there.  Where the voxel is the split's (0,0,0) or (1,1,1) corner (12
+    tetrahedra) the triangle's legs are e_j / 2 and (e_j + e_k) / 2: area 1/8; at
+    the other six corners (2 tetrahedra each) the legs are (e_i + e_j) / 2 and
+    (e_i + e_j + e_k) / 2: area sqrt(2)/8.  A = 3/2 (1 + sqrt 2), enclosed volume
+    24 / 48 = 1/2.  Two separate voxels double the area and V = 2 (voxel count) in
+    pi^(1/3) (6V)^(2/3) / A."""
+    a1 = 1.5 * (1 + math.sqrt(2))
+    one = np.zeros((1, 1, 1), bool)
+    one[0, 0, 0] = True
+    assert M.iso_area(one) == pytest.approx(a1, rel=1e-14)
+    assert M.iso_volume(one) == pytest.approx(0.5, rel=1e-14)
+    assert M.mesh_sphericity(one) == pytest.approx(math.pi ** (1 / 3) * 6 ** (2 / 3) / a1, rel=1e-14)
+    two = np.zeros((1, 1, 4), bool)
+    two[0, 0, 0] = two[0, 0, 3] = True
+    assert M.mesh_sphericity(two) == pytest.approx(math.pi ** (1 / 3) * 12 ** (2 / 3) / (2 * a1), rel=1e-14)

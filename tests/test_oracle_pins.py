@@ -257,3 +257,126 @@ def test_shell_is_distance_one():
             lab = synth.random_labels(rng, shape, n_labels=4, p_bg=0.2, blob=blob)
             D = O.edt_sq(lab)
             np.testing.assert_array_equal(O.shell_mask(lab), (lab != 0) & (D == 1))
+
+
+# --------------------------------------------------------------------------- histogram
+
+def _bin_isqrt(v: int, r2: int) -> int:
+    """The histogram bin by another integer route: the smallest k with
+    k^2 R^2 >= 1024 v is ceil(sqrt(m)) with m = ceil(1024 v / R^2), since k^2 is an
+    integer; ceil(sqrt(m)) = isqrt(m - 1) + 1 for m >= 1."""
+    m = -(-1024 * v // r2)
+    return math.isqrt(m - 1) + 1
+
+
+def test_histogram_hand_values():
+    """With R^2 = 1024 the bin rule 1024 LT <= k^2 R^2 reads LT <= k^2, so a voxel of
+    LT = v lands in bin ceil(sqrt(v)): hand-chosen values at and around squares."""
+    vals = [1, 2, 4, 5, 9, 10, 960, 961, 962, 1023, 1024]
+    want = [1, 2, 2, 3, 3, 4, 31, 31, 32, 32, 32]
+    lab = np.ones((1, len(vals)), dtype=np.int32)
+    lt = np.array([vals], dtype=np.int64)
+    h = O.lt_histogram(lab, lt, np.array([0, 1024]))
+    counts = np.zeros(32)
+    for k in want:
+        counts[k - 1] += 1
+    np.testing.assert_array_equal(h[1], counts / len(vals))
+    assert np.all(np.isnan(h[0]))                      # no background row
+
+
+def test_histogram_ball_all_in_last_bin():
+    """A digital ball has LT = r^2 + 1 = R^2 at every voxel: all of it in bin 32."""
+    m, _ = synth.ball_mask(6)
+    lab = np.pad(m.astype(np.int32), 2)
+    res = O.measure(lab, per_object=False)
+    h = O.lt_histogram(lab, res["lt_sq"], res["max_lt_sq"])
+    want = np.zeros(32)
+    want[31] = 1.0
+    np.testing.assert_array_equal(h[1], want)
+
+
+def test_histogram_against_integer_route_random():
+    """Random LT values and per-label R^2 (LT <= R^2): every voxel's bin equals the
+    isqrt route, and each row sums to 1."""
+    rng = np.random.default_rng(11)
+    n_lab = 7
+    lab = rng.integers(1, n_lab + 1, size=(40, 50)).astype(np.int32)
+    r2 = rng.integers(1, 5000, size=n_lab + 1)
+    r2[0] = 0
+    lt = np.zeros(lab.shape, dtype=np.int64)
+    for l in range(1, n_lab + 1):
+        sel = lab == l
+        lt[sel] = rng.integers(1, r2[l] + 1, size=int(sel.sum()))
+        lt[np.argwhere(sel)[0][0], np.argwhere(sel)[0][1]] = r2[l]   # R^2 is attained
+    h = O.lt_histogram(lab, lt, r2)
+    want = np.zeros((n_lab + 1, 32))
+    for v, l in zip(lt.ravel(), lab.ravel()):
+        want[l, _bin_isqrt(int(v), int(r2[l])) - 1] += 1
+    want[1:] /= want[1:].sum(axis=1, keepdims=True)
+    np.testing.assert_allclose(h[1:], want[1:], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(h[1:].sum(axis=1), 1.0, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- roundness
+
+def _disc_with_spur(r: int, spur: int):
+    """Digital disc {|p|^2 <= r^2} with a one-pixel-wide spur of `spur` pixels
+    leaving the top of the disc along its axis (padded by 2)."""
+    m, _ = synth.disc_mask(r)
+    h, w = m.shape
+    lab = np.zeros((h + spur + 4, w + 4), dtype=np.int32)
+    lab[2 + spur:2 + spur + h, 2:2 + w] = m
+    cx = 2 + w // 2
+    lab[2:2 + spur, cx] = 1
+    return lab
+
+
+def test_roundness_uses_the_shell_only_hand_value():
+    """Disc r = 5 (81 pixels, LT = 26 everywhere: all lie in the centre's ball of
+    D = 26, and no D is larger) with a 10-pixel spur (each spur pixel has D = 1 and
+    lies in no larger ball, so LT = 1).  The disc's contour has 28 pixels (per row y
+    the pixels |x| = w(y) or |x| > w(y +- 1) for half-widths w = 5, 4, 4, 4, 3, 0),
+    the spur's 10 pixels are all contour.  Roundness = mean over the contour of
+    sqrt(LT) / sqrt(max LT) = (28 sqrt 26 + 10) / 38 / sqrt 26 (Method, Roundness);
+    the mean over the whole object would give (81 sqrt 26 + 10) / 91 / sqrt 26."""
+    lab = _disc_with_spur(5, 10)
+    res = O.measure(lab, per_object=False)
+    D = res["dist_sq"]
+    np.testing.assert_array_equal(res["lt_sq"], O.local_thickness_sq_brute(lab, D))
+    assert res["volume"][1] == 91 and res["shell_count"][1] == 38
+    assert res["max_lt_sq"][1] == 26
+    s26 = math.sqrt(26.0)
+    assert res["shell_mean_lt"][1] == pytest.approx((28 * s26 + 10) / 38, rel=1e-14)
+    assert res["roundness"][1] == pytest.approx((28 * s26 + 10) / 38 / s26, rel=1e-14)
+    assert res["mean_lt"][1] == pytest.approx((81 * s26 + 10) / 91, rel=1e-14)
+    assert abs(res["roundness"][1] - res["mean_lt"][1] / s26) > 0.05
+
+
+def test_roundness_shell_3d_ball_with_spur():
+    """3D counterpart: a digital ball r = 4 (LT = 17 everywhere) with a one-voxel
+    spur of 6 voxels along z; the shell mean mixes only the ball's surface voxels
+    (the 6-neighbour shell of the ball, counted here by brute force) with the
+    spur's LT = 1."""
+    m, _ = synth.ball_mask(4)
+    d = m.shape[0]
+    lab = np.zeros((d + 6 + 4, d + 4, d + 4), dtype=np.int32)
+    lab[2 + 6:2 + 6 + d, 2:2 + d, 2:2 + d] = m
+    c = 2 + d // 2
+    lab[2:8, c, c] = 1
+    res = O.measure(lab, per_object=False)
+    np.testing.assert_array_equal(res["lt_sq"], O.local_thickness_sq_brute(lab, res["dist_sq"]))
+    ball = np.zeros_like(lab, dtype=bool)
+    ball[2 + 6:2 + 6 + d, 2:2 + d, 2:2 + d] = m
+    # brute-force 6-neighbour shell of the ball alone; the spur only touches the
+    # ball's pole voxel, which still has four outside faces, so the ball's shell is
+    # the same inside the whole object
+    pad = np.pad(ball, 1)
+    sh = np.zeros_like(ball)
+    for ax in range(3):
+        for s in (-1, 1):
+            sh |= ~np.roll(pad, s, axis=ax)[1:-1, 1:-1, 1:-1]
+    n_ball_sh = int((sh & ball).sum())
+    assert np.all(res["lt_sq"][ball] == 17) and np.all(res["lt_sq"][(lab == 1) & ~ball] == 1)
+    assert res["shell_count"][1] == n_ball_sh + 6
+    s17 = math.sqrt(17.0)
+    assert res["roundness"][1] == pytest.approx((n_ball_sh * s17 + 6) / (n_ball_sh + 6) / s17, rel=1e-14)
