@@ -1,0 +1,176 @@
+"""GPU parity at full size: the 512^3 uint16 benchmark volume checked object by
+object against the CPU oracle (every object, in four shards), bitwise repeat runs
+at that size, and single objects large enough to reach the long-radius code paths
+(squared distances far above the prune tables' range, EDT searches beyond the
+staged halo, paint sources wider than three 64-column chunks).
+
+Distances and local thickness are compared bit-exactly; volume, shell count and
+largest LT exactly; the FP32 measures within 1e-5 relative of the FP64 oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import lt_oracle as O
+from paper_2504_05808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+FLOAT_KEYS = ("mean_lt", "shell_mean_lt", "sphericity", "roundness")
+ORACLE_THREADS = 16          # the host share of one GPU on the test machines
+N_SHARDS = 4
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_05808_amd import lt
+    lt.load()
+    return torch, lt
+
+
+def _to_host(d, t, m):
+    out = dict(dist_sq=d.cpu().numpy().astype(np.int64), lt_sq=t.cpu().numpy().astype(np.int64))
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        out[k] = getattr(m, k).cpu().numpy().astype(np.int64)
+    for k in FLOAT_KEYS:
+        out[k] = getattr(m, k).cpu().numpy().astype(np.float64)
+    return out
+
+
+@pytest.fixture(scope="module")
+def cfg3_run(gpu):
+    torch, lt = gpu
+    lab, meta = synth.cfg3()
+    max_label = int(lab.max())
+    _note(f"cfg3 512^3 uint16 objects={meta['n_objects']}: fused pipeline (the benchmark's launch)")
+    t = torch.from_numpy(lab).cuda()
+    got = _to_host(*lt.pipeline(t, max_label))
+    lt.default_context().sync_status()
+    boxes = O.object_boxes(lab)
+    return dict(lab=lab, t=t, max_label=max_label, got=got, boxes=boxes)
+
+
+def test_cfg3_background_zero(cfg3_run):
+    lab, got = cfg3_run["lab"], cfg3_run["got"]
+    assert np.all(got["lt_sq"][lab == 0] == 0) and np.all(got["dist_sq"][lab == 0] == 0)
+    present = np.zeros(cfg3_run["max_label"] + 1, bool)
+    present[list(cfg3_run["boxes"])] = True
+    assert np.all(got["volume"][~present] == 0)
+    assert np.all(np.isnan(got["sphericity"][~present]))
+
+
+@pytest.mark.parametrize("shard", range(N_SHARDS))
+def test_cfg3_every_object(cfg3_run, shard):
+    """Every object of the benchmark volume, a quarter per test: D and LT on its
+    voxels bit-exact against the oracle's per-object crops, its measures from the
+    oracle's fields."""
+    lab, got, boxes = cfg3_run["lab"], cfg3_run["got"], cfg3_run["boxes"]
+    labels = sorted(boxes)
+    pick = labels[shard::N_SHARDS]
+    _note(f"cfg3 shard {shard}: {len(pick)} objects against the oracle")
+    D, LT, _ = O.fields(lab, labels_subset=pick, threads=ORACLE_THREADS)
+    sel = np.isin(lab, pick)
+    np.testing.assert_array_equal(got["dist_sq"][sel], D[sel])
+    np.testing.assert_array_equal(got["lt_sq"][sel], LT[sel])
+    sub = np.where(sel, lab, 0)
+    sums = O.object_sums(sub, np.where(sel, LT, 0), cfg3_run["max_label"])
+    cf = O.closed_forms(sums, 3)
+    p = np.array(pick)
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        np.testing.assert_array_equal(got[k][p], sums[k][p], err_msg=k)
+    for k in FLOAT_KEYS:
+        np.testing.assert_allclose(got[k][p], cf[k][p], rtol=RTOL, atol=0, err_msg=k)
+
+
+def test_cfg3_repeat_bitwise(gpu, cfg3_run):
+    """Two more runs at 512^3 -- the fused call again and the three separate calls --
+    give the first run's outputs bit for bit (atomics, work-item order and the
+    persistent paint blocks' scheduling must not leak into results)."""
+    torch, lt = gpu
+    t, max_label, first = cfg3_run["t"], cfg3_run["max_label"], cfg3_run["got"]
+    for name, fn in (("fused", lt.pipeline), ("three calls", lt.measure)):
+        _note(f"cfg3 repeat: {name}")
+        again = _to_host(*fn(t, max_label))
+        lt.default_context().sync_status()
+        for k in first:
+            np.testing.assert_array_equal(again[k], first[k], err_msg=f"{name}: {k}")
+
+
+def _run_both(gpu, lab):
+    torch, lt = gpu
+    t = torch.from_numpy(np.ascontiguousarray(lab)).cuda()
+    a = _to_host(*lt.measure(t, int(lab.max())))
+    lt.default_context().sync_status()
+    b = _to_host(*lt.pipeline(t, int(lab.max())))
+    lt.default_context().sync_status()
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"fused vs separate: {k}")
+    return a
+
+
+def _scipy_dsq(mask):
+    """Squared EDT of one object with the image border as background (scipy's exact
+    Euclidean transform; its squares are integers up to rounding)."""
+    e = ndimage.distance_transform_edt(np.pad(mask, 1))[tuple(slice(1, -1) for _ in mask.shape)]
+    return np.where(mask, np.rint(e * e), 0).astype(np.int64)
+
+
+@pytest.mark.parametrize("ndim,r", [(2, 400), (3, 150)])
+def test_large_disc_and_ball(gpu, ndim, r):
+    """A digital disc of radius 400 (D up to 160,801) and ball of radius 150 (D up to
+    22,801): both exceed the prune tables (16,384), the EDT's 32-line staged halo and
+    the paint pass's three-chunk source rows.  D equals scipy's exact transform, LT is
+    r^2 + 1 on every object voxel (the digital disc/ball pin), V is the lattice count,
+    roundness 1."""
+    m, _ = (synth.disc_mask if ndim == 2 else synth.ball_mask)(r)
+    lab = np.pad(m.astype(np.int32), 2)
+    _note(f"large {'disc' if ndim == 2 else 'ball'} r={r} shape={lab.shape}")
+    got = _run_both(gpu, lab)
+    np.testing.assert_array_equal(got["dist_sq"], _scipy_dsq(lab == 1))
+    assert got["dist_sq"].max() > 16384
+    assert np.all(got["lt_sq"][lab == 1] == r * r + 1)
+    assert np.all(got["lt_sq"][lab == 0] == 0)
+    assert got["volume"][1] == int(m.sum())
+    assert got["max_lt_sq"][1] == r * r + 1
+    assert got["shell_count"][1] == int(O.shell_mask(lab).sum())
+    assert got["roundness"][1] == pytest.approx(1.0, rel=RTOL)
+    want_s = (O.sphericity_2d if ndim == 2 else O.sphericity_3d)(float(m.sum()), math.sqrt(r * r + 1))
+    assert got["sphericity"][1] == pytest.approx(want_s, rel=RTOL)
+
+
+def test_large_ellipsoid_sampled_lt(gpu):
+    """An ellipsoid with semi-axes 120 (x) x 70 (y) x 40 (z) (D up to ~1,600, source
+    rows of more than three 64-column chunks): D against scipy, LT at 400 sampled voxels
+    from its definition (largest D(c) over centres c whose open ball holds the
+    voxel)."""
+    m, off = synth.ellipsoid_mask((120.0, 70.0, 40.0), np.eye(3), (0.25, 0.5, 0.75))
+    lab = np.pad(m.astype(np.uint16), 2)
+    _note(f"large ellipsoid shape={lab.shape}")
+    got = _run_both(gpu, lab)
+    D = _scipy_dsq(lab == 1)
+    np.testing.assert_array_equal(got["dist_sq"], D)
+    reach = math.isqrt(int(D.max()) - 1)
+    rng = np.random.default_rng(21)
+    obj = np.argwhere(lab == 1)
+    pick = obj[rng.choice(len(obj), 400, replace=False)]
+    cz, cy, cx = np.argwhere(D == D.max())[0]
+    pick = np.concatenate([pick, [[cz, cy, cx]]])
+    for p in pick:
+        lo = np.maximum(p - reach, 0)
+        hi = np.minimum(p + reach + 1, lab.shape)
+        sub = tuple(slice(a, b) for a, b in zip(lo, hi))
+        g = np.meshgrid(*[np.arange(a, b) for a, b in zip(lo, hi)], indexing="ij")
+        d2 = sum((gg - pp) ** 2 for gg, pp in zip(g, p))
+        want = int(D[sub][d2 < D[sub]].max())
+        assert got["lt_sq"][tuple(p)] == want, tuple(p)
