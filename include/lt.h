@@ -37,6 +37,7 @@
 #ifndef LT_H
 #define LT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -131,6 +132,30 @@ lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, in
 lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                       uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
                       void* stream);
+
+/* Allocation-free form of lt_pipeline, for callers that cannot allocate device
+ * memory while they run (code under stream capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, kernels and outputs as lt_pipeline, bit
+ * for bit, but the scratch memory is a fixed device array of
+ * LT_STATIC_SCRATCH_BYTES inside the library (one copy per device, reserved when
+ * the library's code is loaded on that device and held until the process ends)
+ * instead of the context's growable scratch; the call makes no device allocation
+ * or free, creates no event (the per-kernel profiler is skipped) and does not
+ * synchronise.  The caller still allocates every input and output.
+ *   - a problem whose scratch (lt_pipeline_static_bytes) exceeds the fixed array
+ *     returns LT_E_WORKSPACE before anything is launched; e.g. a 128^3 volume with
+ *     a few hundred labels needs about 50 MiB;
+ *   - all calls on one device share that device's array, and each call leaves its
+ *     contents behind (every kernel initialises what it reads), so calls that
+ *     overlap in time on one device -- on different streams or contexts, or from
+ *     different threads -- race and give undefined results: order them. */
+#define LT_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+lt_status lt_pipeline_static(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                             uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
+                             void* stream);
+/* Scratch bytes lt_pipeline_static needs for this problem (host-only arithmetic;
+ * 0 for an invalid shape or max_label). */
+size_t lt_pipeline_static_bytes(int ndim, const int64_t* shape, uint32_t max_label);
 
 /* Closed forms alone, from per-object sums held on the device (the last step of
  * lt_object_measures; exposed for callers that accumulate their own sums):

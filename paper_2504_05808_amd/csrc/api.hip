@@ -136,6 +136,32 @@ static void build_prune_tables(int n, std::vector<int32_t>& out) {
 static std::once_flag g_tab_once;
 static std::vector<int32_t> g_tab3, g_tab2;
 
+// Fixed scratch of lt_pipeline_static: one copy per device, held until the process
+// ends.  Host code never passes `scratch` itself (in host code the name is a
+// host-side stand-in, not a device address): lt_ctx_create looks up each device's
+// address once with hipGetSymbolAddress and keeps it in g_static_scratch.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)LT_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_static_mu;
+static void* g_static_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device `device`, looked up once.
+static lt_status static_scratch_lookup(int device, void** out) {
+    if (device < 0 || device >= MAX_DEVICES) return set_error(LT_E_ARG, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_scratch[device]) {
+        void* ptr = nullptr;
+        lt_status st = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st) return st;
+        if (!ptr) return set_error(LT_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_static_scratch[device] = ptr;
+    }
+    *out = g_static_scratch[device];
+    return LT_OK;
+}
+
 }  // namespace lt
 
 using namespace lt;
@@ -192,7 +218,8 @@ lt_status lt_ctx_create(lt_ctx** out, int device) {
         (st = hip_check(hipMalloc((void**)&c->d_prune2, b2), "hipMalloc(tab2)")) ||
         (st = hip_check(hipMemcpy(c->d_prune3, g_tab3.data(), b3, hipMemcpyHostToDevice), "copy tab3")) ||
         (st = hip_check(hipMemcpy(c->d_prune2, g_tab2.data(), b2, hipMemcpyHostToDevice), "copy tab2")) ||
-        (st = hip_check(hipMemset(c->d_err, 0, sizeof(uint32_t)), "clear err"))) {
+        (st = hip_check(hipMemset(c->d_err, 0, sizeof(uint32_t)), "clear err")) ||
+        (st = static_scratch_lookup(device, &c->static_scratch))) {
         lt_ctx_destroy(c);
         return st;
     }
@@ -278,6 +305,40 @@ lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
     if ((st = ensure_scratch(ctx, pipeline_scratch_bytes(g, max_label)))) return st;
     return launch_pipeline(ctx, labels, dtype, g, max_label, dist_sq, lt_sq, out, ctx->scratch.ptr,
                            (hipStream_t)stream);
+}
+
+size_t lt_pipeline_static_bytes(int ndim, const int64_t* shape, uint32_t max_label) {
+    Geom g;
+    if (geom_from(ndim, shape, &g) != LT_OK || max_label > (1u << 28)) return 0;
+    return pipeline_scratch_bytes(g, max_label);
+}
+
+lt_status lt_pipeline_static(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                             uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
+                             void* stream) {
+    // sizes first (host arithmetic only), then the common checks, which select the device
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    Geom g;
+    lt_status st = geom_from(ndim, shape, &g);
+    if (st) return st;
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    const size_t need = pipeline_scratch_bytes(g, max_label);
+    if (need > STATIC_SCRATCH_BYTES)
+        return set_error(LT_E_WORKSPACE, "lt_pipeline_static needs %zu bytes of scratch; its fixed scratch holds %zu",
+                         need, STATIC_SCRATCH_BYTES);
+    if ((st = common_checks(ctx, labels, dtype, ndim, shape, &g))) return st;
+    if (!out || !out->volume || !out->shell_count || !out->max_lt_sq || !out->mean_lt ||
+        !out->shell_mean_lt || !out->sphericity || !out->roundness)
+        return set_error(LT_E_ARG, "an output array of lt_measures is NULL");
+    if (g.n > 0 && (!dist_sq || !lt_sq)) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
+    if (!ctx->static_scratch) return set_error(LT_E_NOT_READY, "the context has no fixed scratch address");
+    // the per-kernel profiler creates HIP events; this call makes no such call
+    const bool prof = ctx->profile;
+    ctx->profile = false;
+    st = launch_pipeline(ctx, labels, dtype, g, max_label, dist_sq, lt_sq, out, ctx->static_scratch,
+                         (hipStream_t)stream);
+    ctx->profile = prof;
+    return st;
 }
 
 lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,

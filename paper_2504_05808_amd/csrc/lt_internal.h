@@ -93,6 +93,8 @@ struct lt_ctx {
     int32_t* d_prune3 = nullptr;        // [3][PRUNE_DCAP + 1] (|o|^2 = 1, 2, 3)
     int32_t* d_prune2 = nullptr;        // [2][PRUNE_DCAP + 1] (|o|^2 = 1, 2)
     lt::Scratch scratch;                // grows on demand, freed by lt_ctx_destroy
+    void* static_scratch = nullptr;     // this device's copy of the fixed scratch of
+                                        // lt_pipeline_static (never freed)
     lt::Tuning tune;
     bool profile = false;               // time every launch with HIP events
     std::vector<lt::PendingTiming> pending;

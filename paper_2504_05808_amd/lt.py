@@ -67,6 +67,9 @@ def load():
     lib.lt_thickness.argtypes = [P, P, I, I, i64p, P, U32, P, V]
     lib.lt_object_measures.argtypes = [P, P, I, I, i64p, P, U32, ctypes.POINTER(_Measures), V]
     lib.lt_pipeline.argtypes = [P, P, I, I, i64p, U32, P, P, ctypes.POINTER(_Measures), V]
+    lib.lt_pipeline_static.argtypes = [P, P, I, I, i64p, U32, P, P, ctypes.POINTER(_Measures), V]
+    lib.lt_pipeline_static_bytes.argtypes = [I, i64p, U32]
+    lib.lt_pipeline_static_bytes.restype = ctypes.c_size_t
     lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
     lib.lt_sync_status.argtypes = [P, V]
     lib.lt_ctx_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I)]
@@ -86,6 +89,7 @@ def load():
     lib.lt_last_error.restype = ctypes.c_char_p
     lib.lt_version.restype = ctypes.c_char_p
     for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures", "lt_pipeline",
+              "lt_pipeline_static",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
               "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
               "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
@@ -293,6 +297,27 @@ def pipeline(labels: torch.Tensor, max_label: int, hist: bool = False, out=None,
     ms = _measures_struct(m)
     _check(ctx._lib.lt_pipeline(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), int(max_label), _ptr(d),
                                 _ptr(t), ctypes.byref(ms), _stream(stream)))
+    return d, t, m
+
+
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def pipeline_static_bytes(shape, max_label: int) -> int:
+    """Scratch bytes lt_pipeline_static needs (0 for an invalid shape)."""
+    arr = (ctypes.c_int64 * len(shape))(*shape)
+    return int(load().lt_pipeline_static_bytes(len(shape), arr, int(max_label)))
+
+
+def pipeline_static(labels: torch.Tensor, max_label: int, out, ctx: Context | None = None, stream=None):
+    """lt_pipeline_static: the whole path with the library's fixed scratch (no device
+    allocation inside the call).  `out` = preallocated (dist_sq, lt_sq, Measures)."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    d, t, m = out
+    ms = _measures_struct(m)
+    _check(ctx._lib.lt_pipeline_static(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), int(max_label),
+                                       _ptr(d), _ptr(t), ctypes.byref(ms), _stream(stream)))
     return d, t, m
 
 

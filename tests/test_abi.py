@@ -89,3 +89,18 @@ def test_learned_correction_argument_errors():
     assert lib.lt_bf16_gemm(0, 16, 16, None, 16, 0, None, 16, 0, None, 16, None) == 0
     assert lib.lt_bf16_gemm(16, 16, 16, None, 16, 0, None, 16, 0, None, 16, None) == 1
     assert lib.lt_mlp_state_size() == (3 * 12496 + 4 * 34 + 3 + 2) * 4
+
+
+def test_static_pipeline_size_checks_without_device():
+    """lt_pipeline_static refuses problems beyond its fixed scratch from the sizes
+    alone, before the context is used."""
+    lib = lt.load()
+    fake = ctypes.create_string_buffer(64)      # never dereferenced on these paths
+    ctx = ctypes.cast(fake, ctypes.c_void_p)
+    assert lt.pipeline_static_bytes((128, 128, 128), 300) <= lt.STATIC_SCRATCH_BYTES
+    assert lt.pipeline_static_bytes((512, 512, 512), 2000) > lt.STATIC_SCRATCH_BYTES
+    assert lt.pipeline_static_bytes((1025, 4, 4), 3) == 0
+    big = (ctypes.c_int64 * 3)(512, 512, 512)
+    assert lib.lt_pipeline_static(ctx, ctypes.c_void_p(8), lt.LT_U16, 3, big, 2000, None, None, None, None) == 8
+    assert b"fixed scratch" in lib.lt_last_error()
+    assert lib.lt_pipeline_static(None, ctypes.c_void_p(8), lt.LT_U16, 3, big, 2000, None, None, None, None) == 1
