@@ -152,3 +152,72 @@ def test_mesh_sphericity_single_voxels_hand_value():
     two = np.zeros((1, 1, 4), bool)
     two[0, 0, 0] = two[0, 0, 3] = True
     assert M.mesh_sphericity(two) == pytest.approx(math.pi ** (1 / 3) * 12 ** (2 / 3) / (2 * a1), rel=1e-14)
+
+
+# --------------------------------------------------------------------------- 2D contour
+
+def test_contour_single_pixel_rectangle_and_diagonal_pair():
+    """Marching squares at 0.5 on zero-padded masks, worked by hand: one pixel is cut
+    off in each of its 4 squares (4 x sqrt(2)/2); a w x h block has w - 1 + h - 1
+    unit steps on each pair of sides plus 4 corner cuts, 2(w - 1) + 2(h - 1) +
+    2 sqrt 2; two pixels touching at a corner share one square with both diagonal
+    corners inside (sqrt 2) and have three single-corner squares each."""
+    r2 = math.sqrt(2.0)
+    one = np.ones((1, 1), bool)
+    assert M.contour_length(one) == pytest.approx(2 * r2, rel=1e-15)
+    for w, h in [(1, 1), (3, 5), (7, 2), (1, 6)]:
+        m = np.ones((h, w), bool)
+        assert M.contour_length(m) == pytest.approx(2 * (w - 1) + 2 * (h - 1) + 2 * r2, rel=1e-14)
+    diag = np.eye(2, dtype=bool)
+    assert M.contour_length(diag) == pytest.approx(3 * r2 + r2, rel=1e-14)
+    # an L of three pixels (0, 0), (1, 0), (1, 1): tracing the crossings around it
+    # gives the polygon (-1/2, 0) (0, 1/2) (1/2, 1) (1, 3/2) (3/2, 1) (3/2, 0) (1, -1/2)
+    # (0, -1/2) in (y, x): six diagonal sides of sqrt(2)/2 and two unit sides
+    ell = np.zeros((3, 3), bool)
+    ell[0, 0] = ell[1, 0] = ell[1, 1] = True
+    assert M.contour_length(ell) == pytest.approx(3 * r2 + 2, rel=1e-14)
+
+
+def test_contour_symmetries_and_sphericity():
+    rng = np.random.default_rng(8)
+    for _ in range(4):
+        r = rng.random((9, 13)) < 0.5
+        a = M.contour_length(r)
+        for t in (r.T, r[::-1], r[:, ::-1], r[::-1, ::-1].T):
+            assert M.contour_length(t) == pytest.approx(a, rel=1e-13)
+        assert M.contour_length(r, pad=False) == pytest.approx(M.contour_length(~r, pad=False), rel=1e-13)
+    # a large digital disc: the midpoint contour is a chain of unit and diagonal
+    # steps; a straight edge at angle t in [0, pi/4] costs cos t + (sqrt 2 - 1) sin t
+    # per unit length, on average over t 8 (sqrt 2 - 1) / pi, so the perimeter
+    # sphericity of a large disc tends to pi / (8 (sqrt 2 - 1)) = 0.94806
+    lim = math.pi / (8 * (math.sqrt(2) - 1))
+    errs = []
+    for r in (100, 200, 400):
+        m, _ = synth.disc_mask(r)
+        errs.append(abs(M.contour_sphericity(m) - lim))
+    assert errs[0] < 3e-3 and errs[1] < 1e-3 and errs[2] < 1e-3 and errs[2] < errs[0]
+    assert M.contour_sphericity(np.ones((1, 1), bool)) == pytest.approx(2 * math.sqrt(math.pi) / (2 * math.sqrt(2)))
+
+
+def test_mesh_measures_per_label():
+    """Per-label mesh measures treat other labels as outside: an object's area does
+    not change when another label touches it, and equals the single-mask area."""
+    m, _ = synth.ball_mask(5)
+    lab = np.pad(m.astype(np.int32), 2)
+    alone = M.mesh_measures(lab)
+    crowd = lab.copy()
+    crowd[(crowd == 0) & (np.indices(crowd.shape)[0] < 7)] = 3
+    both = M.mesh_measures(crowd, max_label=4)
+    assert both["volume"][1] == alone["volume"][1] == m.sum()
+    assert both["area"][1] == pytest.approx(M.iso_area(m), rel=1e-14)
+    assert both["area"][1] == pytest.approx(alone["area"][1], rel=1e-14)
+    assert both["sphericity"][1] == pytest.approx(M.mesh_sphericity(m), rel=1e-14)
+    assert both["area"][3] == pytest.approx(M.iso_area(crowd == 3), rel=1e-14)
+    assert np.isnan(both["sphericity"][2]) and np.isnan(both["sphericity"][4]) and both["volume"][2] == 0
+    d, _ = synth.disc_mask(7)
+    lab2 = np.pad(d.astype(np.uint16), 3)
+    lab2[0, :] = 2
+    r = M.mesh_measures(lab2)
+    assert r["area"][1] == pytest.approx(M.contour_length(d), rel=1e-14)
+    # label 2 is a 1 x w row of pixels: 2 (w - 1) + 2 sqrt 2
+    assert r["area"][2] == pytest.approx(2 * (lab2.shape[1] - 1) + 2 * math.sqrt(2.0), rel=1e-14)
