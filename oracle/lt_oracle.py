@@ -265,6 +265,109 @@ def lt_histogram(labels: np.ndarray, lt_sq: np.ndarray, max_lt_sq: np.ndarray) -
 
 
 # ---------------------------------------------------------------------------
+# roughness-filtered roundness and the 0-1 remap (extensions)
+# ---------------------------------------------------------------------------
+#
+# The Discussion expects the influence of surface roughness on the contour /
+# surface roundness to be controllable by filtering the shell values.  The filter
+# used here: a shell voxel's LT is replaced by the largest shell LT found within
+# half-width w along x, then y, then z (2D: x, then y), each step taking only
+# positions that carry the voxel's own label.  Bumps narrower than w lose their
+# small inscribed balls to the larger values around them; w = 0 is the paper's
+# roundness.  The Results note that the observed minimum can map roundness to the
+# standard 0-1 range: R' = (R - m) / (1 - m).
+
+def filtered_shell_lt(labels: np.ndarray, lt_sq: np.ndarray, w: int) -> np.ndarray:
+    """F_w: start from LT_sq on shell voxels and 0 elsewhere; along each axis in turn
+    (x first, z last) a voxel takes the maximum of the current values at offsets
+    -w..w along that axis whose voxel carries its label (outside the image counts as
+    no voxel).  Returned on shell voxels (0 elsewhere)."""
+    lab = np.asarray(labels).astype(np.int64)
+    sh = shell_mask(lab)
+    f = np.where(sh, np.asarray(lt_sq, dtype=np.int64), 0)
+    for ax in reversed(range(lab.ndim)):                # x (last axis) first
+        n = lab.shape[ax]
+        out = f.copy()
+        for o in range(-w, w + 1):
+            if o == 0 or abs(o) >= n:
+                continue
+            src = [slice(None)] * lab.ndim
+            dst = [slice(None)] * lab.ndim
+            src[ax] = slice(max(0, o), n + min(0, o))       # position p + o
+            dst[ax] = slice(max(0, -o), n - max(0, o))      # position p
+            src, dst = tuple(src), tuple(dst)
+            same = lab[src] == lab[dst]
+            out[dst] = np.where(same, np.maximum(out[dst], f[src]), out[dst])
+        f = out
+    return np.where(sh & (lab != 0), f, 0)
+
+
+def filtered_shell_lt_brute(labels: np.ndarray, lt_sq: np.ndarray, w: int) -> np.ndarray:
+    """The same filter by its direct reading: for a shell voxel p of label l, the
+    largest LT_sq(q) over shell voxels q of label l with |q - p| <= w per axis such
+    that the axis-ordered path p -> p + (0,..,dz) -> p + (0, dy, dz) -> q (z step,
+    then y, then x; 2D: y then x) stays on voxels of label l at its corners."""
+    lab = np.asarray(labels).astype(np.int64)
+    lt = np.asarray(lt_sq, dtype=np.int64)
+    sh = shell_mask(lab)
+    out = np.zeros(lab.shape, dtype=np.int64)
+    shape = lab.shape
+    rng = range(-w, w + 1)
+    for p in np.argwhere(sh):
+        p = tuple(int(v) for v in p)
+        l = lab[p]
+        best = 0
+        offs = [(a, b, c) for a in rng for b in rng for c in rng] if lab.ndim == 3 else \
+               [(a, b) for a in rng for b in rng]
+        for o in offs:
+            q = tuple(pi + oi for pi, oi in zip(p, o))
+            if any(v < 0 or v >= n for v, n in zip(q, shape)) or not sh[q] or lab[q] != l:
+                continue
+            # corners of the staircase: change the first axes' coordinates first
+            ok = True
+            for k in range(1, lab.ndim):
+                c = tuple(q[i] if i < k else p[i] for i in range(lab.ndim))
+                if lab[c] != l:
+                    ok = False
+            if ok:
+                best = max(best, int(lt[q]))
+        out[p] = best
+    return out
+
+
+def filtered_roundness(labels: np.ndarray, lt_sq: np.ndarray, w: int, max_label: int | None = None) -> np.ndarray:
+    """Per label: mean over shell voxels of sqrt(F_w) divided by sqrt(max LT_sq);
+    NaN for absent labels."""
+    lab = np.asarray(labels).astype(np.int64)
+    if max_label is None:
+        max_label = int(lab.max()) if lab.size else 0
+    n = max_label + 1
+    F = filtered_shell_lt(lab, lt_sq, w)
+    sh = shell_mask(lab).ravel()
+    l = lab.ravel()[sh]
+    num = np.bincount(l, weights=np.sqrt(F.ravel()[sh].astype(np.float64)), minlength=n)[:n]
+    cnt = np.bincount(l, minlength=n)[:n]
+    mx = np.zeros(n, dtype=np.int64)
+    obj = lab.ravel() != 0
+    np.maximum.at(mx, lab.ravel()[obj], np.asarray(lt_sq, dtype=np.int64).ravel()[obj])
+    out = np.full(n, np.nan)
+    ok = cnt > 0
+    out[ok] = num[ok] / cnt[ok] / np.sqrt(mx[ok].astype(np.float64))
+    return out
+
+
+def remap_roundness(r: np.ndarray, r_min: float | None = None) -> np.ndarray:
+    """(R - m) / (1 - m) with m the given minimum, or the smallest finite R; NaN
+    stays NaN.  When m = 1 every finite R is 1 and maps to 1."""
+    r = np.asarray(r, dtype=np.float64)
+    fin = np.isfinite(r)
+    m = float(r[fin].min()) if r_min is None else float(r_min)
+    out = np.full(r.shape, np.nan)
+    out[fin] = 1.0 if m >= 1.0 else (r[fin] - m) / (1.0 - m)
+    return out
+
+
+# ---------------------------------------------------------------------------
 # whole pipeline
 # ---------------------------------------------------------------------------
 

@@ -323,11 +323,12 @@ def _disc_with_spur(r: int, spur: int):
     """Digital disc {|p|^2 <= r^2} with a one-pixel-wide spur of `spur` pixels
     leaving the top of the disc along its axis (padded by 2)."""
     m, _ = synth.disc_mask(r)
-    h, w = m.shape
+    h, w = m.shape                                  # m has an empty border row / column
     lab = np.zeros((h + spur + 4, w + 4), dtype=np.int32)
-    lab[2 + spur:2 + spur + h, 2:2 + w] = m
+    lab[1 + spur:1 + spur + h, 2:2 + w] = m         # the disc's top pixel at row 2 + spur
     cx = 2 + w // 2
-    lab[2:2 + spur, cx] = 1
+    lab[2:2 + spur, cx] = 1                         # the spur ends right above it
+    assert lab[1 + spur, cx] == 1 and lab[2 + spur, cx] == 1
     return lab
 
 
@@ -380,3 +381,48 @@ def test_roundness_shell_3d_ball_with_spur():
     assert res["shell_count"][1] == n_ball_sh + 6
     s17 = math.sqrt(17.0)
     assert res["roundness"][1] == pytest.approx((n_ball_sh * s17 + 6) / (n_ball_sh + 6) / s17, rel=1e-14)
+
+
+# --------------------------------------------------------------------------- roughness filter
+
+@pytest.mark.parametrize("shape", [(9, 11), (13, 6), (6, 7, 5), (5, 8, 9)])
+def test_filtered_shell_passes_equal_direct_reading(shape):
+    """Axis passes == the direct reading (largest shell value over the window reachable
+    by the axis-ordered staircase through the voxel's own label)."""
+    rng = synth.rng_for(500 + sum(shape))
+    for trial in range(3):
+        lab = synth.random_labels(rng, shape, n_labels=2 + trial, p_bg=0.15 * trial, blob=2)
+        lt = O.local_thickness_sq(O.edt_sq(lab))
+        for w in (0, 1, 2):
+            np.testing.assert_array_equal(O.filtered_shell_lt(lab, lt, w), O.filtered_shell_lt_brute(lab, lt, w))
+
+
+def test_filtered_roundness_hand_values():
+    """The disc r = 5 with a 10-pixel spur: shell LT is 26 on the disc's 28 contour
+    pixels and 1 on the spur.  Half-width 3 lifts the three spur pixels within 3 of
+    the disc's top pixel to 26, half-width 10 lifts all of them, w = 0 is the plain
+    roundness."""
+    lab = _disc_with_spur(5, 10)
+    res = O.measure(lab, per_object=False)
+    lt = res["lt_sq"]
+    s26 = math.sqrt(26.0)
+    assert O.filtered_roundness(lab, lt, 0)[1] == pytest.approx(res["roundness"][1], rel=1e-14)
+    assert O.filtered_roundness(lab, lt, 1)[1] == pytest.approx((29 * s26 + 9) / 38 / s26, rel=1e-14)
+    assert O.filtered_roundness(lab, lt, 3)[1] == pytest.approx((31 * s26 + 7) / 38 / s26, rel=1e-14)
+    assert O.filtered_roundness(lab, lt, 10)[1] == pytest.approx(1.0, rel=1e-14)
+    r = [O.filtered_roundness(lab, lt, w)[1] for w in range(12)]
+    assert all(b >= a - 1e-15 for a, b in zip(r, r[1:])) and r[-1] <= 1.0 + 1e-12
+
+
+def test_filtered_roundness_ball_and_remap():
+    m, _ = synth.ball_mask(5)
+    lab = np.pad(m.astype(np.int32), 2)
+    lt = O.local_thickness_sq(O.edt_sq(lab))
+    for w in (0, 2, 4):
+        assert O.filtered_roundness(lab, lt, w)[1] == pytest.approx(1.0, rel=1e-14)
+    r = np.array([np.nan, 0.4, 0.7, 1.0, 0.55])
+    out = O.remap_roundness(r)
+    np.testing.assert_allclose(out[1:], [0.0, 0.5, 1.0, 0.25], rtol=1e-14)
+    assert np.isnan(out[0])
+    np.testing.assert_allclose(O.remap_roundness(r, 0.2)[1:], [0.25, 0.625, 1.0, 0.4375], rtol=1e-14)
+    assert np.all(O.remap_roundness(np.array([1.0, 1.0]))== 1.0)
