@@ -360,6 +360,44 @@ def mlp_bench(args):
     net.close()
 
 
+def extensions_bench(ctx, lab, lt_sq, max_label: int, reps: int = 10) -> dict:
+    """The calls beyond the step, each timed alone on the resident volume (outside
+    the step's timed region): kernel times from the library's per-launch HIP events
+    and algorithmic GB/s against the HBM peak."""
+    import torch
+
+    from paper_2504_05808_amd import lt
+    N = lab.numel()
+    lb = lab.element_size()
+    out = {}
+
+    def timed(name, fn, kernel_bytes_map):
+        fn()
+        ctx.sync_status()
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ctx.sync_status()
+        ks = {k: v[0] / v[1] for k, v in prof.items()}
+        rec = {"ms": round(sum(v[0] for v in prof.values()) / reps, 4),
+               "kernel_ms": {k: round(v, 4) for k, v in ks.items()}}
+        for k, b in kernel_bytes_map.items():
+            if k in ks:
+                gbs = b / (ks[k] * 1e-3) / 1e9
+                rec.setdefault("kernel_GBs", {})[k] = round(gbs, 1)
+                rec.setdefault("hbm_frac", {})[k] = round(gbs / HBM_PEAK_GBS, 4)
+        out[name] = rec
+
+    # mesh-based surface measures: one streaming read of the labels
+    timed("mesh_measures", lambda: lt.mesh_measures(lab, max_label, ctx=ctx),
+          {"mesh_area3d": lb * N})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,6 +537,8 @@ def main():
     pipe_bytes = 36.0 * N
     pipe_gbs = pipe_bytes / (ms * 1e-3) / 1e9
 
+    ext = extensions_bench(ctx, lab, t, max_label)
+
     cpu = None
     if not args.no_cpu_baseline:
         # the host share of one GPU on the test machines is 16 cores
@@ -534,6 +574,7 @@ def main():
         "kernel_GBs": {k: round(v["GBs"], 1) for k, v in kernels.items() if "GBs" in v},
         "ball_cover": None if work is None else {"work_points": work, "kept_centres": kept,
                                                  "points_per_object_voxel": work / (f_obj * N)},
+        "extensions": ext,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

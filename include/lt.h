@@ -170,6 +170,40 @@ lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
                           float* shell_mean_lt, float* sphericity, float* roundness,
                           void* stream);
 
+/* Mesh-based surface measures per object: the sphericity baseline the method is
+ * compared with (Related work; Experiments, Benchmark methods: the object is meshed
+ * by marching cubes / marching squares and the mesh area / contour length enters
+ * Wadell's sphericity, Background Eq. 1, or the perimeter sphericity).
+ * The surface of object l is the iso-surface at 1/2 of its own 0/1 mask (other
+ * labels and everything outside the image are 0), linear inside the simplices of
+ * the lattice:
+ *   3D: each unit cube split into the six Freudenthal tetrahedra along its
+ *       (0,0,0)-(1,1,1) diagonal (marching tetrahedra); area = sum of the
+ *       triangles / parallelograms through the midpoints of the edges that join
+ *       an inside and an outside corner;
+ *   2D: marching squares with segments between side midpoints (a square with two
+ *       diagonal inside corners cuts off each inside corner).
+ * Outputs, each [max_label + 1] and indexed by label, any of them may be NULL (not
+ * all three):
+ *   volume      uint64 voxel (pixel) count V;
+ *   area        float surface area (3D) or contour length (2D), 0 for absent labels;
+ *   sphericity  float, 3D pi^(1/3) (6V)^(2/3) / area, 2D 2 sqrt(pi V) / length;
+ *               NaN where V = 0.
+ * Areas are accumulated in Q.32 fixed point, so results are independent of the
+ * order of the device's atomics.  Labels above max_label set LT_E_LABEL_RANGE
+ * (lt_sync_status) and count as background. */
+lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                           const int64_t* shape, uint32_t max_label, uint64_t* volume,
+                           float* area, float* sphericity, void* stream);
+
+/* The per-cell table behind lt_mesh_measures, as the device sums it (Q.32
+ * rounded): ndim 3 writes 256 entries, the surface area inside a unit cube whose
+ * corners with bit k of the index set are inside (corner k = (x, y, z) offset
+ * (k & 1, (k >> 1) & 1, k >> 2)); ndim 2 writes 16 entries, the contour length in a
+ * unit square (corner k = (x, y) offset (k & 1, k >> 1)).  `out` is a HOST array.
+ * Needs no device. */
+lt_status lt_mesh_table(int ndim, double* out);
+
 /* Synchronise `stream`, read and clear the context's device error word.
  * Returns LT_OK, LT_E_LABEL_RANGE, LT_E_OVERFLOW or LT_E_HIP. */
 lt_status lt_sync_status(lt_ctx* ctx, void* stream);

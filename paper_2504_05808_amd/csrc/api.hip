@@ -307,6 +307,24 @@ lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
                            (hipStream_t)stream);
 }
 
+lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                           uint32_t max_label, uint64_t* volume, float* area, float* sphericity, void* stream) {
+    Geom g;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st) return st;
+    if (!volume && !area && !sphericity) return set_error(LT_E_ARG, "volume, area and sphericity are all NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    if ((st = ensure_scratch(ctx, mesh_scratch_bytes(max_label)))) return st;
+    return launch_mesh(ctx, labels, dtype, g, max_label, volume, area, sphericity, ctx->scratch.ptr,
+                       (hipStream_t)stream);
+}
+
+lt_status lt_mesh_table(int ndim, double* out) {
+    if (ndim != 2 && ndim != 3) return set_error(LT_E_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
+    if (!out) return set_error(LT_E_ARG, "out is NULL");
+    return mesh_table_host(ndim, out);
+}
+
 size_t lt_pipeline_static_bytes(int ndim, const int64_t* shape, uint32_t max_label) {
     Geom g;
     if (geom_from(ndim, shape, &g) != LT_OK || max_label > (1u << 28)) return 0;

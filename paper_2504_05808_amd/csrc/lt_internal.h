@@ -96,6 +96,7 @@ struct lt_ctx {
     void* static_scratch = nullptr;     // this device's copy of the fixed scratch of
                                         // lt_pipeline_static (never freed)
     lt::Tuning tune;
+    bool mesh_ready = false;            // mesh area tables copied to this device
     bool profile = false;               // time every launch with HIP events
     std::vector<lt::PendingTiming> pending;
     std::vector<lt::KernelTotal> totals;
@@ -153,6 +154,12 @@ lt_status launch_measures_zero(lt_ctx* ctx, uint32_t max_label, const lt_measure
 lt_status launch_measures_finish(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                                  const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
                                  void* scratch, hipStream_t s);
+// Mesh-based surface measures (mesh.hip): per-label voxel count, iso-surface area
+// (3D) or contour length (2D) and mesh sphericity; any output may be NULL.
+size_t mesh_scratch_bytes(uint32_t max_label);
+lt_status mesh_table_host(int ndim, double* out);
+lt_status launch_mesh(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
+                      uint64_t* volume, float* area, float* sphericity, void* scratch, hipStream_t s);
 // Scratch for the fused pipeline: EDT, then thickness with the measures' scratch
 // placed after the thickness region (both live during the paint pass).
 size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label);

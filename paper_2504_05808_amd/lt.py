@@ -71,6 +71,7 @@ def load():
     lib.lt_pipeline_static_bytes.argtypes = [I, i64p, U32]
     lib.lt_pipeline_static_bytes.restype = ctypes.c_size_t
     lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
+    lib.lt_mesh_measures.argtypes = [P, P, I, I, i64p, U32, P, P, P, V]
     lib.lt_sync_status.argtypes = [P, V]
     lib.lt_ctx_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I)]
     lib.lt_profile_enable.argtypes = [P, I]
@@ -89,7 +90,7 @@ def load():
     lib.lt_last_error.restype = ctypes.c_char_p
     lib.lt_version.restype = ctypes.c_char_p
     for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures", "lt_pipeline",
-              "lt_pipeline_static",
+              "lt_pipeline_static", "lt_mesh_measures",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
               "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
               "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
@@ -329,6 +330,21 @@ def measure(labels: torch.Tensor, max_label: int, hist: bool = False, ctx: Conte
     t = thickness(labels, d, max_label, ctx=ctx, stream=stream)
     m = object_measures(labels, t, max_label, hist=hist, ctx=ctx, stream=stream)
     return d, t, m
+
+
+def mesh_measures(labels: torch.Tensor, max_label: int, ctx: Context | None = None, stream=None) -> dict:
+    """Per-object voxel count, mesh area (3D marching tetrahedra) or contour length
+    (2D marching squares) and mesh sphericity, see lt_mesh_measures."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    n = int(max_label) + 1
+    out = dict(volume=torch.empty(n, dtype=torch.uint64, device=lab.device),
+               area=torch.empty(n, dtype=torch.float32, device=lab.device),
+               sphericity=torch.empty(n, dtype=torch.float32, device=lab.device))
+    _check(ctx._lib.lt_mesh_measures(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), int(max_label),
+                                     _ptr(out["volume"]), _ptr(out["area"]), _ptr(out["sphericity"]),
+                                     _stream(stream)))
+    return out
 
 
 def version() -> str:

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2504_05808_amd import lt
@@ -104,3 +105,27 @@ def test_static_pipeline_size_checks_without_device():
     assert lib.lt_pipeline_static(ctx, ctypes.c_void_p(8), lt.LT_U16, 3, big, 2000, None, None, None, None) == 8
     assert b"fixed scratch" in lib.lt_last_error()
     assert lib.lt_pipeline_static(None, ctypes.c_void_p(8), lt.LT_U16, 3, big, 2000, None, None, None, None) == 1
+
+
+def test_mesh_tables_match_the_oracle_per_cell():
+    """The library's host-built cell tables (lt_mesh_table) against the mesh oracle
+    evaluated on one unit cube / square per inside pattern (no padding, so only that
+    cell counts).  Q.32 rounding of the table entries is below 2^-32."""
+    from oracle import mesh_area as M
+    lib = lt.load()
+    lib.lt_mesh_table.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    cube = (ctypes.c_double * 256)()
+    assert lib.lt_mesh_table(3, cube) == 0
+    for m in range(256):
+        mask = np.zeros((2, 2, 2), dtype=bool)
+        for k in range(8):
+            mask[k >> 2, (k >> 1) & 1, k & 1] = (m >> k) & 1
+        assert cube[m] == pytest.approx(M.iso_area(mask, pad=False), abs=2 ** -31), m
+    sq = (ctypes.c_double * 16)()
+    assert lib.lt_mesh_table(2, sq) == 0
+    for m in range(16):
+        mask = np.zeros((2, 2), dtype=bool)
+        for k in range(4):
+            mask[k >> 1, k & 1] = (m >> k) & 1
+        assert sq[m] == pytest.approx(M.contour_length(mask, pad=False), abs=2 ** -31), m
+    assert lib.lt_mesh_table(4, cube) == 3
