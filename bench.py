@@ -360,7 +360,7 @@ def mlp_bench(args):
     net.close()
 
 
-def extensions_bench(ctx, lab, lt_sq, max_label: int, reps: int = 10) -> dict:
+def extensions_bench(ctx, lab, dist_sq, lt_sq, max_label: int, reps: int = 10) -> dict:
     """The calls beyond the step, each timed alone on the resident volume (outside
     the step's timed region): kernel times from the library's per-launch HIP events
     and algorithmic GB/s against the HBM peak."""
@@ -395,6 +395,10 @@ def extensions_bench(ctx, lab, lt_sq, max_label: int, reps: int = 10) -> dict:
     # mesh-based surface measures: one streaming read of the labels
     timed("mesh_measures", lambda: lt.mesh_measures(lab, max_label, ctx=ctx),
           {"mesh_area3d": lb * N})
+    # roughness-filtered roundness, half-width 2: three separable window passes
+    # (x: labels, D, LT -> F; y: labels, F -> F; z: labels, F, D, LT -> per-label sums)
+    timed("filtered_roundness_w2", lambda: lt.filtered_roundness(lab, dist_sq, lt_sq, max_label, 2, ctx=ctx),
+          {"rough_x": (lb + 12) * N, "rough_y": (lb + 8) * N, "rough_z_final": (lb + 12) * N})
     return out
 
 
@@ -537,7 +541,7 @@ def main():
     pipe_bytes = 36.0 * N
     pipe_gbs = pipe_bytes / (ms * 1e-3) / 1e9
 
-    ext = extensions_bench(ctx, lab, t, max_label)
+    ext = extensions_bench(ctx, lab, d, t, max_label)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -196,6 +196,35 @@ lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int 
                            const int64_t* shape, uint32_t max_label, uint64_t* volume,
                            float* area, float* sphericity, void* stream);
 
+/* Roughness-filtered roundness (Discussion: the roundness approximation responds
+ * to surface roughness, an influence that filtering can control).  The shell
+ * values are filtered before the mean of Method, Roundness is taken:
+ *   F_0(p) = lt_sq[p] on shell voxels (dist_sq[p] == 1: a face neighbour is of
+ *            another label or outside the image), 0 elsewhere;
+ *   then along x, then y, then z (2D: x, then y):
+ *   F(p) = max{ F(p + o e_axis) : |o| <= half_width, labels[p + o e_axis] == labels[p] };
+ *   roundness[l] = mean over l's shell voxels of sqrt(F) / sqrt(max lt_sq over l).
+ * half_width = 0 gives the plain roundness of lt_object_measures; bumps narrower
+ * than about half_width stop lowering the value.  dist_sq and lt_sq are lt_edt's
+ * and lt_thickness's outputs for the same labels (device, [N] int32);
+ * roundness is a device array of max_label + 1 floats (NaN for labels without
+ * voxels).  half_width outside 0..LT_ROUGH_MAX_HALF_WIDTH returns LT_E_ARG.  The
+ * context's scratch grows to two int32 fields of the image's size. */
+#define LT_ROUGH_MAX_HALF_WIDTH 16
+lt_status lt_filtered_roundness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                                const int64_t* shape, const int32_t* dist_sq, const int32_t* lt_sq,
+                                uint32_t max_label, int half_width, float* roundness, void* stream);
+
+/* Map roundness values onto 0..1 through a minimum m (Results, performance on the
+ * 2D charts: the smallest observed value anchors the scale):
+ *   out[i] = (roundness[i] - m) / (1 - m) for finite entries, NaN entries stay NaN,
+ *   and every finite entry becomes 1 when m >= 1.
+ * m = r_min, or, when r_min is NaN, the smallest finite entry of `roundness`
+ * (found on the device).  roundness and out are device arrays of n floats (they
+ * may be the same array).  FP32 arithmetic. */
+lt_status lt_remap_roundness(lt_ctx* ctx, const float* roundness, uint32_t n, float r_min, float* out,
+                             void* stream);
+
 /* The per-cell table behind lt_mesh_measures, as the device sums it (Q.32
  * rounded): ndim 3 writes 256 entries, the surface area inside a unit cube whose
  * corners with bit k of the index set are inside (corner k = (x, y, z) offset

@@ -1,4 +1,5 @@
 // C-ABI entry points of liblt: context, argument checks, dispatch, error text.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -317,6 +318,34 @@ lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int 
     if ((st = ensure_scratch(ctx, mesh_scratch_bytes(max_label)))) return st;
     return launch_mesh(ctx, labels, dtype, g, max_label, volume, area, sphericity, ctx->scratch.ptr,
                        (hipStream_t)stream);
+}
+
+lt_status lt_filtered_roundness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                                const int32_t* dist_sq, const int32_t* lt_sq, uint32_t max_label, int half_width,
+                                float* roundness, void* stream) {
+    if (half_width < 0 || half_width > LT_ROUGH_MAX_HALF_WIDTH)
+        return set_error(LT_E_ARG, "half_width %d outside 0..%d", half_width, LT_ROUGH_MAX_HALF_WIDTH);
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    if (!roundness) return set_error(LT_E_ARG, "roundness is NULL");
+    Geom g;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st) return st;
+    if (g.n > 0 && (!dist_sq || !lt_sq)) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
+    if ((st = ensure_scratch(ctx, rough_scratch_bytes(g, max_label)))) return st;
+    return launch_filtered_roundness(ctx, labels, dtype, g, dist_sq, lt_sq, max_label, half_width, roundness,
+                                     ctx->scratch.ptr, (hipStream_t)stream);
+}
+
+lt_status lt_remap_roundness(lt_ctx* ctx, const float* roundness, uint32_t n, float r_min, float* out,
+                             void* stream) {
+    if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
+    if (n == 0) return LT_OK;
+    if (!roundness || !out) return set_error(LT_E_ARG, "roundness or out is NULL");
+    if (!isnan(r_min) && !isfinite(r_min)) return set_error(LT_E_ARG, "r_min must be finite or NaN");
+    lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    if (st) return st;
+    if ((st = ensure_scratch(ctx, 256))) return st;
+    return launch_remap(ctx, roundness, n, r_min, out, ctx->scratch.ptr, (hipStream_t)stream);
 }
 
 lt_status lt_mesh_table(int ndim, double* out) {

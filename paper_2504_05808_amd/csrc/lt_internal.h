@@ -160,6 +160,14 @@ size_t mesh_scratch_bytes(uint32_t max_label);
 lt_status mesh_table_host(int ndim, double* out);
 lt_status launch_mesh(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
                       uint64_t* volume, float* area, float* sphericity, void* scratch, hipStream_t s);
+// Roughness-filtered roundness (roughness.hip): separable same-label window maxima
+// of the shell LT, reduced per label; and the 0-1 remap of roundness values.
+size_t rough_scratch_bytes(const Geom& g, uint32_t max_label);
+lt_status launch_filtered_roundness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
+                                    const int32_t* D, const int32_t* lt, uint32_t max_label, int w,
+                                    float* roundness, void* scratch, hipStream_t s);
+lt_status launch_remap(lt_ctx* ctx, const float* r, uint32_t n, float r_min, float* out, void* scratch,
+                       hipStream_t s);
 // Scratch for the fused pipeline: EDT, then thickness with the measures' scratch
 // placed after the thickness region (both live during the paint pass).
 size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label);

@@ -72,6 +72,8 @@ def load():
     lib.lt_pipeline_static_bytes.restype = ctypes.c_size_t
     lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
     lib.lt_mesh_measures.argtypes = [P, P, I, I, i64p, U32, P, P, P, V]
+    lib.lt_filtered_roundness.argtypes = [P, P, I, I, i64p, P, P, U32, I, P, V]
+    lib.lt_remap_roundness.argtypes = [P, P, U32, ctypes.c_float, P, V]
     lib.lt_sync_status.argtypes = [P, V]
     lib.lt_ctx_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(I)]
     lib.lt_profile_enable.argtypes = [P, I]
@@ -90,7 +92,7 @@ def load():
     lib.lt_last_error.restype = ctypes.c_char_p
     lib.lt_version.restype = ctypes.c_char_p
     for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures", "lt_pipeline",
-              "lt_pipeline_static", "lt_mesh_measures",
+              "lt_pipeline_static", "lt_mesh_measures", "lt_filtered_roundness", "lt_remap_roundness",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
               "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
               "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
@@ -344,6 +346,34 @@ def mesh_measures(labels: torch.Tensor, max_label: int, ctx: Context | None = No
     _check(ctx._lib.lt_mesh_measures(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), int(max_label),
                                      _ptr(out["volume"]), _ptr(out["area"]), _ptr(out["sphericity"]),
                                      _stream(stream)))
+    return out
+
+
+def filtered_roundness(labels: torch.Tensor, dist_sq: torch.Tensor, lt_sq: torch.Tensor, max_label: int,
+                       half_width: int, out: torch.Tensor | None = None, ctx: Context | None = None,
+                       stream=None) -> torch.Tensor:
+    """Per-object roundness from the filtered shell local thickness (float32,
+    indexed by label), see lt_filtered_roundness."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    out = out if out is not None else torch.empty(int(max_label) + 1, dtype=torch.float32, device=lab.device)
+    _check(ctx._lib.lt_filtered_roundness(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab),
+                                          _ptr(dist_sq.contiguous()), _ptr(lt_sq.contiguous()), int(max_label),
+                                          int(half_width), _ptr(out), _stream(stream)))
+    return out
+
+
+def remap_roundness(roundness: torch.Tensor, r_min: float | None = None, out: torch.Tensor | None = None,
+                    ctx: Context | None = None, stream=None) -> torch.Tensor:
+    """(R - m) / (1 - m) with m = r_min or the smallest finite R, see lt_remap_roundness."""
+    ctx = ctx or default_context()
+    r = roundness.contiguous()
+    if r.dtype != torch.float32 or not r.is_cuda:
+        raise TypeError("roundness must be a float32 device tensor")
+    out = out if out is not None else torch.empty_like(r)
+    m = float("nan") if r_min is None else float(r_min)
+    _check(ctx._lib.lt_remap_roundness(ctx.handle, _ptr(r), r.numel(), ctypes.c_float(m), _ptr(out),
+                                       _stream(stream)))
     return out
 
 

@@ -129,3 +129,26 @@ def test_mesh_tables_match_the_oracle_per_cell():
             mask[k >> 1, k & 1] = (m >> k) & 1
         assert sq[m] == pytest.approx(M.contour_length(mask, pad=False), abs=2 ** -31), m
     assert lib.lt_mesh_table(4, cube) == 3
+
+
+def test_filtered_roundness_and_remap_argument_errors():
+    """Half-width range, NULL outputs and r_min are checked before any device use."""
+    lib = lt.load()
+    fake = ctypes.create_string_buffer(64)
+    ctx = ctypes.cast(fake, ctypes.c_void_p)
+    shape = (ctypes.c_int64 * 3)(4, 4, 4)
+    p = ctypes.c_void_p(8)
+    f = lib.lt_filtered_roundness
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    assert f(ctx, p, lt.LT_U16, 3, shape, p, p, 5, 17, p, None) == 1
+    assert b"half_width" in lib.lt_last_error()
+    assert f(ctx, p, lt.LT_U16, 3, shape, p, p, 5, -1, p, None) == 1
+    assert f(ctx, p, lt.LT_U16, 3, shape, p, p, 5, 2, None, None) == 1
+    assert f(None, p, lt.LT_U16, 3, shape, p, p, 5, 2, p, None) == 1
+    r = lib.lt_remap_roundness
+    r.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
+    assert r(None, p, 4, float("nan"), p, None) == 1
+    assert r(ctx, p, 0, float("nan"), p, None) == 0              # nothing to do
+    assert r(ctx, None, 4, float("nan"), p, None) == 1
+    assert r(ctx, p, 4, float("inf"), p, None) == 1
