@@ -72,9 +72,9 @@ def _load():
     if _lib is None:
         lib = ctypes.CDLL(build())
         p64 = ctypes.POINTER(ctypes.c_int64)
-        lib.oracle_edt.argtypes = [p64, ctypes.c_int, p64, p64]
+        lib.oracle_edt.argtypes = [p64, ctypes.c_int, p64, p64, p64]
         lib.oracle_edt.restype = ctypes.c_int
-        lib.oracle_lt.argtypes = [p64, ctypes.c_int, p64, p64, p64]
+        lib.oracle_lt.argtypes = [p64, ctypes.c_int, p64, p64, p64, p64]
         lib.oracle_lt.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -84,30 +84,50 @@ def _p64(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
 
 
+def _weights(weights, ndim: int):
+    """Squared voxel spacings as an int64 array of ndim positive integers, or None
+    for unit spacing."""
+    if weights is None:
+        return None
+    w = np.ascontiguousarray(weights, dtype=np.int64)
+    if w.shape != (ndim,) or np.any(w < 1):
+        raise ValueError(f"weights must be {ndim} positive integers")
+    return w
+
+
+def _wptr(w):
+    return _p64(w) if w is not None else None
+
+
 # ---------------------------------------------------------------------------
 # tier 1 (C): distance transform and local thickness on a whole image
 # ---------------------------------------------------------------------------
 
-def edt_sq(labels: np.ndarray) -> np.ndarray:
+def edt_sq(labels: np.ndarray, weights=None) -> np.ndarray:
     """Per-label squared EDT: D(p) = min |p - q|^2 over q outside the image or with
-    L(q) != L(p); 0 on background.  int64."""
+    L(q) != L(p); 0 on background.  int64.  With `weights` (the squared voxel
+    spacings, ndim positive integers along (z, y, x) or (y, x)) |o|^2 is the weighted
+    sum of the squared offsets."""
     lab = np.ascontiguousarray(labels, dtype=np.int64)
     if lab.ndim not in (2, 3):
         raise ValueError("labels must be 2D or 3D")
+    w = _weights(weights, lab.ndim)
     out = np.empty(lab.shape, dtype=np.int64)
     shape = np.array(lab.shape, dtype=np.int64)
-    if _load().oracle_edt(_p64(lab), lab.ndim, _p64(shape), _p64(out)) != 0:
+    if _load().oracle_edt(_p64(lab), lab.ndim, _p64(shape), _wptr(w), _p64(out)) != 0:
         raise RuntimeError("oracle_edt failed")
     return out
 
 
-def local_thickness_sq(dist_sq: np.ndarray, return_work: bool = False):
-    """Squared local thickness: LT(p) = max{D(x) : |p - x|^2 < D(x)}; 0 on background."""
+def local_thickness_sq(dist_sq: np.ndarray, return_work: bool = False, weights=None):
+    """Squared local thickness: LT(p) = max{D(x) : |p - x|^2 < D(x)}; 0 on background
+    (|.|^2 weighted as in edt_sq when `weights` is given)."""
     d = np.ascontiguousarray(dist_sq, dtype=np.int64)
+    w = _weights(weights, d.ndim)
     out = np.empty(d.shape, dtype=np.int64)
     shape = np.array(d.shape, dtype=np.int64)
     work = np.zeros(1, dtype=np.int64)
-    if _load().oracle_lt(_p64(d), d.ndim, _p64(shape), _p64(out), _p64(work)) != 0:
+    if _load().oracle_lt(_p64(d), d.ndim, _p64(shape), _wptr(w), _p64(out), _p64(work)) != 0:
         raise RuntimeError("oracle_lt failed")
     return (out, int(work[0])) if return_work else out
 
@@ -116,10 +136,13 @@ def local_thickness_sq(dist_sq: np.ndarray, return_work: bool = False):
 # tier 0 (numpy): literal minima / maxima over all pairs, tiny images only
 # ---------------------------------------------------------------------------
 
-def edt_sq_brute(labels: np.ndarray) -> np.ndarray:
-    """Literal D: for every object voxel, the minimum of |p - q|^2 over all q of the
-    image grown by a one-voxel frame (the frame is outside, hence background)."""
+def edt_sq_brute(labels: np.ndarray, weights=None) -> np.ndarray:
+    """Literal D: for every object voxel, the minimum of |p - q|^2 (weighted by the
+    squared spacings when given) over all q of the image grown by a one-voxel frame
+    (the frame is outside, hence background; a nearest outside point along any
+    direction first crosses the frame)."""
     lab = np.asarray(labels)
+    w = np.ones(lab.ndim, np.int64) if weights is None else np.asarray(weights, np.int64)
     pad = np.pad(lab.astype(np.int64), 1, constant_values=0)
     qcoords = np.argwhere(np.ones(pad.shape, bool)) - 1          # image coordinates
     qlab = pad.ravel()
@@ -127,20 +150,21 @@ def edt_sq_brute(labels: np.ndarray) -> np.ndarray:
     for p in np.argwhere(lab != 0):
         l = lab[tuple(p)]
         other = qcoords[qlab != l]
-        out[tuple(p)] = int(((other - p) ** 2).sum(axis=1).min())
+        out[tuple(p)] = int((w * (other - p) ** 2).sum(axis=1).min())
     return out
 
 
-def local_thickness_sq_brute(labels: np.ndarray, dist_sq: np.ndarray) -> np.ndarray:
+def local_thickness_sq_brute(labels: np.ndarray, dist_sq: np.ndarray, weights=None) -> np.ndarray:
     """Literal LT: for every object voxel p, the maximum D(x) over all x with
-    D(x) > 0 and |p - x|^2 < D(x)."""
+    D(x) > 0 and |p - x|^2 < D(x) (weighted as in edt_sq_brute)."""
     lab = np.asarray(labels)
+    w = np.ones(lab.ndim, np.int64) if weights is None else np.asarray(weights, np.int64)
     d = np.asarray(dist_sq, dtype=np.int64)
     xs = np.argwhere(d > 0)
     dx = d[tuple(xs.T)]
     out = np.zeros(lab.shape, dtype=np.int64)
     for p in np.argwhere(lab != 0):
-        dist2 = ((xs - p) ** 2).sum(axis=1)
+        dist2 = (w * (xs - p) ** 2).sum(axis=1)
         cover = dist2 < dx
         out[tuple(p)] = int(dx[cover].max())
     return out
@@ -218,10 +242,14 @@ def sphericity_2d(area: float, mean_lt: float) -> float:
     return 2.0 * math.sqrt(math.pi * area) / ramanujan_perimeter(a, b)
 
 
-def closed_forms(sums: dict, ndim: int) -> dict:
+def closed_forms(sums: dict, ndim: int, voxel_size: float = 1.0) -> dict:
     """Per-label FP64 mean LT, max LT, shell mean LT, sphericity and roundness.
-    Entries with V = 0 (background, absent labels) are NaN."""
-    V = sums["volume"].astype(np.float64)
+    Entries with V = 0 (background, absent labels) are NaN.  `voxel_size` is the
+    physical volume (area) of one voxel (pixel): with squared spacings w it is
+    sqrt(prod w), and V (A) in the sphericity is the voxel count times it; local
+    thickness values are already physical lengths."""
+    V = sums["volume"].astype(np.float64)              # voxel counts
+    Vp = V * float(voxel_size)                         # physical volume (area)
     n = len(V)
     mean_lt = np.full(n, np.nan)
     max_lt = np.full(n, np.nan)
@@ -236,7 +264,7 @@ def closed_forms(sums: dict, ndim: int) -> dict:
         if sums["shell_count"][l] > 0:
             shell_mean[l] = sums["shell_sum_lt"][l] / sums["shell_count"][l]
             rnd[l] = shell_mean[l] / max_lt[l]
-        sph[l] = (sphericity_3d if ndim == 3 else sphericity_2d)(V[l], mean_lt[l])
+        sph[l] = (sphericity_3d if ndim == 3 else sphericity_2d)(Vp[l], mean_lt[l])
     return dict(mean_lt=mean_lt, max_lt=max_lt, shell_mean_lt=shell_mean, sphericity=sph,
                 roundness=rnd)
 
@@ -384,7 +412,7 @@ def object_boxes(labels: np.ndarray):
     return boxes
 
 
-def _crop_fields(lab: np.ndarray, l: int, box):
+def _crop_fields(lab: np.ndarray, l: int, box, weights=None):
     """D and LT of label l computed on its box grown by one voxel (clipped to the
     image).  Exact: the nearest non-l position of an l voxel always lies in that
     grown box (clamping any nearer candidate into the box keeps it non-l and no
@@ -393,13 +421,13 @@ def _crop_fields(lab: np.ndarray, l: int, box):
     hi = [min(s, b + 1) for b, s in zip(box[1], lab.shape)]
     sl = tuple(slice(a, b) for a, b in zip(lo, hi))
     sub = (lab[sl] == l).astype(np.int64)
-    d = edt_sq(sub)
-    lt, work = local_thickness_sq(d, return_work=True)
+    d = edt_sq(sub, weights)
+    lt, work = local_thickness_sq(d, return_work=True, weights=weights)
     return sl, sub.astype(bool), d, lt, work
 
 
 def fields(labels: np.ndarray, per_object: bool | None = None, threads: int | None = None,
-           labels_subset=None):
+           labels_subset=None, weights=None):
     """D and LT for a whole label image, either directly or one object crop at a time
     (threads run crops in parallel; the C calls release the GIL).  With
     ``labels_subset`` only those labels are filled (other voxels stay -1)."""
@@ -407,8 +435,8 @@ def fields(labels: np.ndarray, per_object: bool | None = None, threads: int | No
     if per_object is None:
         per_object = lab.size > 64 ** 3 or labels_subset is not None
     if not per_object:
-        d = edt_sq(lab)
-        lt, work = local_thickness_sq(d, return_work=True)
+        d = edt_sq(lab, weights)
+        lt, work = local_thickness_sq(d, return_work=True, weights=weights)
         return d, lt, work
     boxes = object_boxes(lab)
     todo = sorted(boxes) if labels_subset is None else [int(l) for l in labels_subset]
@@ -417,19 +445,22 @@ def fields(labels: np.ndarray, per_object: bool | None = None, threads: int | No
     LT = np.full(lab.shape, fill, dtype=np.int64)
     works = 0
     with ThreadPoolExecutor(max_workers=threads or os.cpu_count() or 1) as ex:
-        for sl, m, d, lt, work in ex.map(lambda l: _crop_fields(lab, l, boxes[l]), todo):
+        for sl, m, d, lt, work in ex.map(lambda l: _crop_fields(lab, l, boxes[l], weights), todo):
             D[sl][m] = d[m]
             LT[sl][m] = lt[m]
             works += work
     return D, LT, works
 
 
-def measure(labels: np.ndarray, max_label: int | None = None, **kw) -> dict:
-    """Full oracle pipeline: D, LT, per-label sums and closed forms (FP64)."""
+def measure(labels: np.ndarray, max_label: int | None = None, weights=None, **kw) -> dict:
+    """Full oracle pipeline: D, LT, per-label sums and closed forms (FP64).  With
+    `weights` (squared voxel spacings) distances are weighted and volumes are
+    physical (voxel count times sqrt(prod weights))."""
     lab = np.asarray(labels)
-    D, LT, work = fields(lab, **kw)
+    D, LT, work = fields(lab, weights=weights, **kw)
     sums = object_sums(lab, LT, max_label)
     out = dict(dist_sq=D, lt_sq=LT, ball_work=work)
     out.update(sums)
-    out.update(closed_forms(sums, lab.ndim))
+    vs = 1.0 if weights is None else math.sqrt(float(np.prod(np.asarray(weights, np.float64))))
+    out.update(closed_forms(sums, lab.ndim, voxel_size=vs))
     return out
