@@ -395,6 +395,18 @@ def extensions_bench(ctx, lab, dist_sq, lt_sq, max_label: int, reps: int = 10) -
     # mesh-based surface measures: one streaming read of the labels
     timed("mesh_measures", lambda: lt.mesh_measures(lab, max_label, ctx=ctx),
           {"mesh_area3d": lb * N})
+    # anisotropic spacing: the volume sampled every second slice (256 x 512 x 512,
+    # slices twice as thick as pixels: squared spacings 4, 1, 1), the whole path
+    lab_a = lab[::2].contiguous()
+    Na = lab_a.numel()
+    out_a = (torch.empty_like(lab_a, dtype=torch.int32), torch.empty_like(lab_a, dtype=torch.int32),
+             lt.alloc_measures(max_label + 1, lab.device))
+    timed("pipeline_aniso_4_1_1", lambda: lt.pipeline_aniso(lab_a, max_label, (4, 1, 1), out=out_a, ctx=ctx), {})
+    rec = out["pipeline_aniso_4_1_1"]
+    rec["workload"] = "512^3 volume, every second slice: 256 x 512 x 512 uint16, squared spacings (4, 1, 1)"
+    rec["voxels_per_s"] = Na / (rec["ms"] * 1e-3)
+    rec["pipeline_hbm_frac"] = round(36.0 * Na / (rec["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    del out_a, lab_a
     # roughness-filtered roundness, half-width 2: three separable window passes
     # (x: labels, D, LT -> F; y: labels, F -> F; z: labels, F, D, LT -> per-label sums)
     timed("filtered_roundness_w2", lambda: lt.filtered_roundness(lab, dist_sq, lt_sq, max_label, 2, ctx=ctx),

@@ -170,6 +170,35 @@ lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
                           float* shell_mean_lt, float* sphericity, float* roundness,
                           void* stream);
 
+/* ---------------------------------------------------------- anisotropic spacing
+ * The same four steps for voxels that are longer along some axes (micro-CT stacks
+ * often have thicker slices than pixels; the paper's data use unit spacing, for
+ * which these calls equal the plain ones).  sq_spacing is a HOST array of ndim
+ * integers w in 1..LT_MAX_SQ_SPACING, the squared voxel spacings along (z, y, x) or
+ * (y, x) in a common length unit u (spacing sqrt(w) u).  Every squared distance
+ * becomes w_z dz^2 + w_y dy^2 + w_x dx^2 (units u^2), so:
+ *   dist_sq[p] = min over q outside the image or of another label of that sum;
+ *   lt_sq[p]   = max{ dist_sq[x] : weighted |p - x|^2 < dist_sq[x] } (balls are
+ *                ellipsoids in index space, spheres in space);
+ *   measures: LT radii are lengths in u; the sphericity takes the physical volume
+ *   (area) V = voxel count x sqrt(w_z w_y w_x) (sqrt(w_y w_x) in 2D); volume and
+ *   shell_count stay voxel counts; the shell is the face-neighbour shell.
+ * Results are exact integers as in the plain calls.  LT_E_ARG when a weight is
+ * outside the range or when the largest possible squared distance,
+ * min_a w_a ((n_a + 1) / 2)^2, exceeds 2^19 - 1 (3D) or 2^24 (2D). */
+#define LT_MAX_SQ_SPACING 255
+lt_status lt_edt_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                       const int32_t* sq_spacing, int32_t* dist_sq, void* stream);
+lt_status lt_thickness_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                             const int64_t* shape, const int32_t* sq_spacing, const int32_t* dist_sq,
+                             uint32_t max_label, int32_t* lt_sq, void* stream);
+lt_status lt_object_measures_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
+                                   const int64_t* shape, const int32_t* sq_spacing, const int32_t* lt_sq,
+                                   uint32_t max_label, const lt_measures* out, void* stream);
+lt_status lt_pipeline_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                            const int32_t* sq_spacing, uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq,
+                            const lt_measures* out, void* stream);
+
 /* Mesh-based surface measures per object: the sphericity baseline the method is
  * compared with (Related work; Experiments, Benchmark methods: the object is meshed
  * by marching cubes / marching squares and the mesh area / contour length enters

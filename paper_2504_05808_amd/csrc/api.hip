@@ -1,6 +1,7 @@
 // C-ABI entry points of liblt: context, argument checks, dispatch, error text.
 #include <math.h>
 #include <stdarg.h>
+#include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -67,18 +68,18 @@ size_t pipeline_scratch_bytes(const Geom& g, uint32_t max_label) {
 
 lt_status launch_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
                           int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out, void* scratch,
-                          hipStream_t s) {
+                          hipStream_t s, const Spacing* sp) {
     void* mscr = (char*)scratch + pipeline_measures_offset(g, max_label);
     int32_t* bb = (int32_t*)((char*)scratch + pipeline_boxes_offset(g, max_label));
     const BoxTarget box{bb, max_label + 1, max_label};
     lt_status st = LT_OK;
     if (g.n > 0 && !(st = launch_init_boxes(ctx, bb, max_label + 1, s)))
-        st = launch_edt(ctx, labels, dt, g, dist_sq, scratch, s, &box);
+        st = launch_edt(ctx, labels, dt, g, dist_sq, scratch, s, &box, sp);
     MeasureSums sums;
     if (!st) st = launch_measures_zero(ctx, max_label, out, mscr, s, &sums);
     if (!st && g.n > 0)
-        st = launch_thickness(ctx, labels, dt, g, dist_sq, max_label, lt_sq, scratch, s, &sums, bb);
-    if (!st) st = launch_measures_finish(ctx, labels, dt, g, lt_sq, max_label, out, mscr, s);
+        st = launch_thickness(ctx, labels, dt, g, dist_sq, max_label, lt_sq, scratch, s, &sums, bb, sp);
+    if (!st) st = launch_measures_finish(ctx, labels, dt, g, lt_sq, max_label, out, mscr, s, sp ? sp->vsize : 1.0f);
     return st;
 }
 
@@ -132,6 +133,98 @@ static void build_prune_tables(int n, std::vector<int32_t>& out) {
             if (b > run) run = b;
         }
     }
+}
+
+// Weighted containment tables: for the offset classes c (which axes the neighbour
+// offset o_c moves along: bit 2 z, bit 1 y, bit 0 x; c = bits - 1) and d <= PRUNE_DCAP,
+// T_c[d] = max{ |q - o_c|_w^2 : |q|_w^2 < d } with |q|_w^2 = wz qz^2 + wy qy^2 + wx qx^2.
+// A ball of squared radius d centred at x lies in the open ball of x + o (for any o
+// of class c: the lattice ball is symmetric under sign flips of each axis) iff
+// D(x + o) > T_c[d].  2D: classes over (y, x) only.
+static void build_prune_tables_weighted(int ndim, const Spacing& sp, std::vector<int32_t>& out) {
+    const int dcap = PRUNE_DCAP;
+    const int nc = ndim == 3 ? 7 : 3;
+    std::vector<int32_t> best((size_t)nc * (dcap + 1), -1);
+    auto reach = [&](int w) {                    // largest r with w r^2 < dcap
+        int r = 0;
+        while (w * (r + 1) * (r + 1) < dcap) ++r;
+        return r;
+    };
+    const int rz = ndim == 3 ? reach(sp.wz) : 0, ry = reach(sp.wy), rx = reach(sp.wx);
+    for (int qz = -rz; qz <= rz; ++qz)
+        for (int qy = -ry; qy <= ry; ++qy)
+            for (int qx = -rx; qx <= rx; ++qx) {
+                const int m = sp.wz * qz * qz + sp.wy * qy * qy + sp.wx * qx * qx;
+                if (m >= dcap) continue;
+                for (int c = 0; c < nc; ++c) {
+                    const int bits = c + 1;
+                    const int oz = ndim == 3 ? (bits >> 2) & 1 : 0, oy = (bits >> 1) & 1, ox = bits & 1;
+                    const int v = sp.wz * (qz - oz) * (qz - oz) + sp.wy * (qy - oy) * (qy - oy) +
+                                  sp.wx * (qx - ox) * (qx - ox);
+                    int32_t& b = best[(size_t)c * (dcap + 1) + m];
+                    if (v > b) b = v;
+                }
+            }
+    out.assign((size_t)nc * (dcap + 1), -1);
+    for (int c = 0; c < nc; ++c) {
+        int32_t run = -1;                        // max over |q|_w^2 < d
+        for (int d = 0; d <= dcap; ++d) {
+            out[(size_t)c * (dcap + 1) + d] = run;
+            const int32_t b = best[(size_t)c * (dcap + 1) + d];
+            if (b > run) run = b;
+        }
+    }
+}
+
+lt_status prune_tables_weighted(lt_ctx* ctx, int ndim, const Spacing& sp, const int32_t** out) {
+    const std::array<int, 4> key{ndim, ndim == 3 ? sp.wz : 1, sp.wy, sp.wx};
+    for (const auto& e : ctx->prune_w)
+        if (e.first == key) {
+            *out = e.second;
+            return LT_OK;
+        }
+    std::vector<int32_t> tab;
+    build_prune_tables_weighted(ndim, sp, tab);
+    int32_t* d = nullptr;
+    const size_t bytes = tab.size() * sizeof(int32_t);
+    lt_status st = hip_check(hipMalloc((void**)&d, bytes), "hipMalloc(weighted prune tables)");
+    if (st) return st;
+    if ((st = hip_check(hipMemcpy(d, tab.data(), bytes, hipMemcpyHostToDevice), "copy weighted prune tables"))) {
+        (void)hipFree(d);
+        return st;
+    }
+    ctx->prune_w.push_back({key, d});
+    *out = d;
+    return LT_OK;
+}
+
+// Squared spacings from the caller: ndim integers in 1..LT_MAX_SQ_SPACING along
+// (z, y, x) or (y, x).  Every squared distance of the image is at most
+// min_a w_a ((n_a + 1) / 2)^2 (the border is that close along each axis); the
+// weighted kernels need it below 2^19 in 3D (packed front entries) and 2^24 in 2D.
+static lt_status spacing_from(int ndim, const Geom& g, const int32_t* sq, Spacing* sp) {
+    if (!sq) return set_error(LT_E_ARG, "sq_spacing is NULL");
+    int w[3] = {1, 1, 1};
+    for (int i = 0; i < ndim; ++i) {
+        if (sq[i] < 1 || sq[i] > LT_MAX_SQ_SPACING)
+            return set_error(LT_E_ARG, "squared spacing %d outside 1..%d", (int)sq[i], LT_MAX_SQ_SPACING);
+        w[3 - ndim + i] = sq[i];
+    }
+    sp->wz = w[0];
+    sp->wy = w[1];
+    sp->wx = w[2];
+    sp->vsize = (float)sqrt((double)w[0] * w[1] * w[2]);
+    const int n[3] = {g.nz, g.ny, g.nx};
+    int64_t bound = INT64_MAX;
+    for (int a = 3 - ndim; a < 3; ++a) {
+        const int64_t h = (n[a] + 1) / 2;
+        bound = std::min(bound, (int64_t)w[a] * h * h);
+    }
+    const int64_t lim = ndim == 3 ? (int64_t)ZF_D_MASK : (int64_t)1 << 24;
+    if (bound > lim)
+        return set_error(LT_E_ARG, "squared distances up to %lld exceed %lld for this shape and spacing",
+                         (long long)bound, (long long)lim);
+    return LT_OK;
 }
 
 static std::once_flag g_tab_once;
@@ -236,6 +329,7 @@ lt_status lt_ctx_destroy(lt_ctx* ctx) {
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     if (ctx->d_prune3) (void)hipFree(ctx->d_prune3);
     if (ctx->d_prune2) (void)hipFree(ctx->d_prune2);
+    for (auto& e : ctx->prune_w) (void)hipFree(e.second);
     delete ctx;
     return LT_OK;
 }
@@ -318,6 +412,67 @@ lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int 
     if ((st = ensure_scratch(ctx, mesh_scratch_bytes(max_label)))) return st;
     return launch_mesh(ctx, labels, dtype, g, max_label, volume, area, sphericity, ctx->scratch.ptr,
                        (hipStream_t)stream);
+}
+
+lt_status lt_edt_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                       const int32_t* sq_spacing, int32_t* dist_sq, void* stream) {
+    Geom g;
+    Spacing sp;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st || (st = spacing_from(ndim, g, sq_spacing, &sp))) return st;
+    if (g.n == 0) return LT_OK;
+    if (!dist_sq) return set_error(LT_E_ARG, "dist_sq is NULL");
+    if ((st = ensure_scratch(ctx, edt_scratch_bytes(g)))) return st;
+    return launch_edt(ctx, labels, dtype, g, dist_sq, ctx->scratch.ptr, (hipStream_t)stream, nullptr, &sp);
+}
+
+lt_status lt_thickness_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                             const int32_t* sq_spacing, const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
+                             void* stream) {
+    Geom g;
+    Spacing sp;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st || (st = spacing_from(ndim, g, sq_spacing, &sp))) return st;
+    if (g.n == 0) return LT_OK;
+    if (!dist_sq || !lt_sq) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    if ((st = ensure_scratch(ctx, thickness_scratch_bytes(g, max_label)))) return st;
+    return launch_thickness(ctx, labels, dtype, g, dist_sq, max_label, lt_sq, ctx->scratch.ptr, (hipStream_t)stream,
+                            nullptr, nullptr, &sp);
+}
+
+lt_status lt_object_measures_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                                   const int32_t* sq_spacing, const int32_t* lt_sq, uint32_t max_label,
+                                   const lt_measures* out, void* stream) {
+    Geom g;
+    Spacing sp;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st || (st = spacing_from(ndim, g, sq_spacing, &sp))) return st;
+    if (!out || !out->volume || !out->shell_count || !out->max_lt_sq || !out->mean_lt ||
+        !out->shell_mean_lt || !out->sphericity || !out->roundness)
+        return set_error(LT_E_ARG, "an output array of lt_measures is NULL");
+    if (g.n > 0 && !lt_sq) return set_error(LT_E_ARG, "lt_sq is NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    if ((st = ensure_scratch(ctx, measures_scratch_bytes(max_label)))) return st;
+    return launch_measures(ctx, labels, dtype, g, lt_sq, max_label, out, ctx->scratch.ptr, (hipStream_t)stream,
+                           sp.vsize);
+}
+
+lt_status lt_pipeline_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
+                            const int32_t* sq_spacing, uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq,
+                            const lt_measures* out, void* stream) {
+    Geom g;
+    Spacing sp;
+    lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
+    if (st || (st = spacing_from(ndim, g, sq_spacing, &sp))) return st;
+    if (!out || !out->volume || !out->shell_count || !out->max_lt_sq || !out->mean_lt ||
+        !out->shell_mean_lt || !out->sphericity || !out->roundness)
+        return set_error(LT_E_ARG, "an output array of lt_measures is NULL");
+    if (g.n > 0 && (!dist_sq || !lt_sq)) return set_error(LT_E_ARG, "dist_sq or lt_sq is NULL");
+    if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
+    if ((st = ensure_scratch(ctx, pipeline_scratch_bytes(g, max_label)))) return st;
+    return launch_pipeline(ctx, labels, dtype, g, max_label, dist_sq, lt_sq, out, ctx->scratch.ptr,
+                           (hipStream_t)stream, &sp);
 }
 
 lt_status lt_filtered_roundness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,

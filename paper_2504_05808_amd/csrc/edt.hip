@@ -170,6 +170,9 @@ __global__ void init_boxes(int32_t* bb, uint32_t nlab) {
 // stages its 11-bit input g in both direction forms instead: the low half holds g,
 // or 0 below a run end (LINE_BLK_DN), the high half g, or 0 past a run start
 // (LINE_BLK_UP), so a step's candidate is a 24-bit square of one half.
+// With W (anisotropic spacing) a step k along the axis costs wa k^2 (wa = the
+// squared spacing of the axis) and the y pass stages w_x g^2 in the word form of
+// the z pass.
 constexpr int LINE_T = 64, LINE_H = 32, LINE_ROWS = LINE_T + 2 * LINE_H;
 constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LINE_BLK_UP - 1u;
 
@@ -190,10 +193,11 @@ __device__ __forceinline__ int line_pair(uint32_t wl, uint32_t wh) {
     return min(line_down(wl), line_up(wh));
 }
 
-template <typename L, int AXIS, typename F>
+template <typename L, int AXIS, typename F, bool W = false>
 __global__ void __launch_bounds__(512)
 edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __restrict__ out,
-              int nx, int ny, int nz) {
+              int nx, int ny, int nz, int wa = 1, int wprev = 1) {
+    constexpr bool HALF = AXIS == 1 && !W;                 // the y pass's half-word form
     // one LDS word per staged position: first the labels (to derive the boundary
     // bits), then the value with its bits; the values wait in registers meanwhile
     __shared__ uint32_t s_val[LINE_ROWS * 64];
@@ -219,10 +223,11 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
             const size_t i = base + (size_t)a * stride + x;
             lv = lab[i];
             fv = (int)f[i];
+            if (W && AXIS == 1) fv = wprev * fv * fv;          // weighted g^2
         }
         s_val[r * 64 + tx] = (uint32_t)lv;
         vals[q] = (uint32_t)fv;
-        if (AXIS == 1 && fv > 0) obj |= 1u << q;
+        if (HALF && fv > 0) obj |= 1u << q;
     }
     __syncthreads();
 #pragma unroll
@@ -231,7 +236,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         const uint32_t lv = s_val[r * 64 + tx];
         const bool dn = r + 1 >= LINE_ROWS || s_val[(r + 1) * 64 + tx] != lv;
         const bool up = r == 0 || s_val[(r - 1) * 64 + tx] != lv;
-        if (AXIS == 1)
+        if (HALF)
             vals[q] = (dn ? 0u : vals[q]) | ((up ? 0u : vals[q]) << 16);
         else
             vals[q] |= (dn ? LINE_BLK_DN : 0u) | (up ? LINE_BLK_UP : 0u);
@@ -247,7 +252,7 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         const size_t i = base + (size_t)p * stride + x;
         const uint32_t w0 = s_val[r * 64 + tx];
         int best;                                          // 0: background, no search
-        if (AXIS == 1) {
+        if (HALF) {
             // g from either half; a run of one position (both halves 0) has D2 = 1
             const int g0 = (int)max(w0 & 0xffffu, w0 >> 16);
             best = g0 ? __mul24(g0, g0) : (int)((obj >> ((r - ty) >> 3)) & 1u);
@@ -258,41 +263,43 @@ edt_pass_line(const L* __restrict__ lab, const F* __restrict__ f, int32_t* __res
         // happens best <= k^2 and every later candidate, at least (k + 1)^2, loses, so
         // the search needs no per-direction stop: it ends when k^2 reaches best.
         int k = 1;
+        // step cost wa k^2 (k^2 unless W)
+        auto cost = [&](int kk) { return W ? wa * kk * kk : kk * kk; };
         // staged range, four steps per round: the eight words are loaded first so
         // that their latencies overlap; the steps are then applied in order.  The
         // wave runs while any lane still searches (a lane already done only takes
         // candidates that cannot lower its best), so the loop needs no exec masks.
-        while (__ballot(k * k < best) != 0ull && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
+        while (__ballot(cost(k) < best) != 0ull && r - k - 3 >= 0 && r + k + 3 < LINE_ROWS) {
             uint32_t wl[4], wh[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 wl[u] = s_val[(r - k - u) * 64 + tx];
                 wh[u] = s_val[(r + k + u) * 64 + tx];
             }
-            int kk = k * k;
+            int kk = cost(k);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                best = min(best, kk + line_pair<AXIS>(wl[u], wh[u]));
-                kk += 2 * (k + u) + 1;
+                best = min(best, kk + line_pair<HALF ? 1 : 2>(wl[u], wh[u]));
+                kk += (W ? wa : 1) * (2 * (k + u) + 1);
             }
             k += 4;
         }
-        for (; __ballot(k * k < best) != 0ull; ++k) {
+        for (; __ballot(cost(k) < best) != 0ull; ++k) {
             if (r - k < 0 || r + k >= LINE_ROWS) break;           // leave the staged range
             const uint32_t wl = s_val[(r - k) * 64 + tx], wh = s_val[(r + k) * 64 + tx];
-            best = min(best, k * k + line_pair<AXIS>(wl, wh));
+            best = min(best, cost(k) + line_pair<HALF ? 1 : 2>(wl, wh));
         }
-        const L l = k * k < best ? lab[i] : L(0);
-        for (; k * k < best; ++k) {                                // beyond the halo
-            const int kk = k * k;
+        const L l = cost(k) < best ? lab[i] : L(0);
+        for (; cost(k) < best; ++k) {                              // beyond the halo
+            const int kk = cost(k);
             int cl = kk, ch = kk;
             if (p - k >= 0 && lab[i - k * stride] == l) {
                 const int v = (int)f[i - k * stride];
-                cl += AXIS == 1 ? v * v : v;
+                cl += AXIS == 1 ? (W ? wprev : 1) * v * v : v;
             }
             if (p + k < n && lab[i + k * stride] == l) {
                 const int v = (int)f[i + k * stride];
-                ch += AXIS == 1 ? v * v : v;
+                ch += AXIS == 1 ? (W ? wprev : 1) * v * v : v;
             }
             best = min(best, min(cl, ch));
         }
@@ -307,7 +314,7 @@ size_t edt_scratch_bytes(const Geom& g) {
 
 template <typename L>
 static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* dist, void* scratch,
-                           hipStream_t s, const BoxTarget* box) {
+                           hipStream_t s, const BoxTarget* box, const Spacing& sp) {
     // scratch: g (uint16) then d2 (int32, 3D only)
     const size_t gbytes = (g.n * sizeof(uint16_t) + 255) & ~size_t(255);
     uint16_t* gx = (uint16_t*)scratch;
@@ -329,28 +336,33 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
     const int bx = (g.nx + 63) / 64;
     const dim3 gy(bx, (g.ny + LINE_T - 1) / LINE_T, g.nz);
     const dim3 gz(bx, g.ny, (g.nz + LINE_T - 1) / LINE_T);
-    if (g.ndim == 2) {
+    const bool w = !sp.unit();
+    int32_t* ydst = g.ndim == 2 ? dist : d2;
+    {
         ProfScope _p(ctx, s, "edt_pass_y");
-        edt_pass_line<L, 1, uint16_t><<<gy, lblock, 0, s>>>(lab, gx, dist, g.nx, g.ny, g.nz);
-    } else {
-        {
-            ProfScope _p(ctx, s, "edt_pass_y");
-            edt_pass_line<L, 1, uint16_t><<<gy, lblock, 0, s>>>(lab, gx, d2, g.nx, g.ny, g.nz);
-        }
-        {
-            ProfScope _p(ctx, s, "edt_pass_z");
+        if (w)
+            edt_pass_line<L, 1, uint16_t, true><<<gy, lblock, 0, s>>>(lab, gx, ydst, g.nx, g.ny, g.nz, sp.wy, sp.wx);
+        else
+            edt_pass_line<L, 1, uint16_t><<<gy, lblock, 0, s>>>(lab, gx, ydst, g.nx, g.ny, g.nz);
+    }
+    if (g.ndim == 3) {
+        ProfScope _p(ctx, s, "edt_pass_z");
+        if (w)
+            edt_pass_line<L, 2, int32_t, true><<<gz, lblock, 0, s>>>(lab, d2, dist, g.nx, g.ny, g.nz, sp.wz, 1);
+        else
             edt_pass_line<L, 2, int32_t><<<gz, lblock, 0, s>>>(lab, d2, dist, g.nx, g.ny, g.nz);
-        }
     }
     return hip_check(hipGetLastError(), "edt launch");
 }
 
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, int32_t* dist_sq,
-                     void* scratch, hipStream_t s, const BoxTarget* box) {
+                     void* scratch, hipStream_t s, const BoxTarget* box, const Spacing* sp) {
+    const Spacing unit;
+    const Spacing& spc = sp ? *sp : unit;
     switch (dt) {
-        case LT_U16: return edt_typed(ctx, (const uint16_t*)labels, g, dist_sq, scratch, s, box);
-        case LT_I32: return edt_typed(ctx, (const int32_t*)labels, g, dist_sq, scratch, s, box);
-        case LT_U32: return edt_typed(ctx, (const uint32_t*)labels, g, dist_sq, scratch, s, box);
+        case LT_U16: return edt_typed(ctx, (const uint16_t*)labels, g, dist_sq, scratch, s, box, spc);
+        case LT_I32: return edt_typed(ctx, (const int32_t*)labels, g, dist_sq, scratch, s, box, spc);
+        case LT_U32: return edt_typed(ctx, (const uint32_t*)labels, g, dist_sq, scratch, s, box, spc);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <array>
+#include <utility>
 #include <vector>
 
 #include "../../include/lt.h"
@@ -52,6 +54,15 @@ constexpr int SPILL_ROW_SLICE = 32;
 constexpr uint32_t CL_Z_BITS = 11;
 constexpr uint32_t CL_Z_MASK = (1u << CL_Z_BITS) - 1u;
 
+// Anisotropic spacing: integer squared voxel spacings along z, y, x (a distance
+// step along axis a costs w_a), and the physical voxel volume (area in 2D)
+// sqrt(prod w) that the sphericity's V takes.  Unit spacing is the paper's case.
+struct Spacing {
+    int wz = 1, wy = 1, wx = 1;
+    float vsize = 1.0f;
+    bool unit() const { return wz == 1 && wy == 1 && wx == 1; }
+};
+
 struct Geom {
     int ndim;
     int nz, ny, nx;     // ndim == 2: nz == 1
@@ -95,6 +106,9 @@ struct lt_ctx {
     lt::Scratch scratch;                // grows on demand, freed by lt_ctx_destroy
     void* static_scratch = nullptr;     // this device's copy of the fixed scratch of
                                         // lt_pipeline_static (never freed)
+    // weighted prune tables per spacing (ndim, wz, wy, wx) -> device table; kept until
+    // the context is destroyed (a table in use by queued kernels is never rewritten)
+    std::vector<std::pair<std::array<int, 4>, int32_t*>> prune_w;
     lt::Tuning tune;
     bool mesh_ready = false;            // mesh area tables copied to this device
     bool profile = false;               // time every launch with HIP events
@@ -125,7 +139,8 @@ size_t edt_scratch_bytes(const Geom& g);
 // With `box` set, the x pass also records the per-label bounding boxes (fused
 // pipeline; the boxes must have been emptied first).
 lt_status launch_edt(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
-                     int32_t* dist_sq, void* scratch, hipStream_t s, const BoxTarget* box = nullptr);
+                     int32_t* dist_sq, void* scratch, hipStream_t s, const BoxTarget* box = nullptr,
+                     const Spacing* sp = nullptr);
 lt_status launch_init_boxes(lt_ctx* ctx, int32_t* bb, uint32_t nlab, hipStream_t s);
 size_t thickness_scratch_bytes(const Geom& g, uint32_t max_label);
 int paint_tile_rows(lt_ctx* ctx);
@@ -144,16 +159,19 @@ struct MeasureSums {
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
                            void* scratch, hipStream_t s, const MeasureSums* sums = nullptr,
-                           int32_t* boxes = nullptr);
+                           int32_t* boxes = nullptr, const Spacing* sp = nullptr);
+// Containment tables of the weighted prune for this spacing (one row per offset
+// class: 7 in 3D, 3 in 2D), built on the host on first use and kept by the context.
+lt_status prune_tables_weighted(lt_ctx* ctx, int ndim, const Spacing& sp, const int32_t** out);
 size_t measures_scratch_bytes(uint32_t max_label);
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                           const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
-                          void* scratch, hipStream_t s);
+                          void* scratch, hipStream_t s, float vsize = 1.0f);
 lt_status launch_measures_zero(lt_ctx* ctx, uint32_t max_label, const lt_measures* out, void* scratch,
                                hipStream_t s, MeasureSums* sums);
 lt_status launch_measures_finish(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                                  const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
-                                 void* scratch, hipStream_t s);
+                                 void* scratch, hipStream_t s, float vsize = 1.0f);
 // Mesh-based surface measures (mesh.hip): per-label voxel count, iso-surface area
 // (3D) or contour length (2D) and mesh sphericity; any output may be NULL.
 size_t mesh_scratch_bytes(uint32_t max_label);
@@ -175,7 +193,7 @@ size_t pipeline_measures_offset(const Geom& g, uint32_t max_label);
 // EDT -> thickness with fused sums -> histogram and closed forms.
 lt_status launch_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g, uint32_t max_label,
                           int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out, void* scratch,
-                          hipStream_t s);
+                          hipStream_t s, const Spacing* sp = nullptr);
 lt_status launch_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q,
                               const int32_t* max_lt_sq, const uint64_t* shell_count,
                               const uint64_t* shell_sum_q, uint32_t n, int ndim,
@@ -243,6 +261,17 @@ __device__ __forceinline__ int isqrt_floor(int n) {
 
 // Largest h with h*h < b, for b >= 1 (the reach of an open ball of squared radius b).
 __device__ __forceinline__ int open_reach(int b) { return isqrt_floor(b - 1); }
+
+// Largest h >= 0 with w h^2 < b, for 1 <= b < 2^24 and 1 <= w < 256: the reach of an
+// open ball of squared radius b along an axis whose squared spacing is w.  The
+// float estimate of sqrt((b - 1) / w) is within one of h; integer fix-ups make it
+// exact.
+__device__ __forceinline__ int open_reach_w(int b, int w) {
+    int h = (int)__fsqrt_rn((float)(b - 1) / (float)w);
+    if (w * h * h >= b) --h;
+    else if (w * (h + 1) * (h + 1) < b) ++h;
+    return h;
+}
 
 template <typename L>
 __device__ __forceinline__ bool label_negative(L v) {

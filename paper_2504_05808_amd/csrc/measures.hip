@@ -223,7 +223,8 @@ __global__ void closed_forms_kernel(const uint64_t* __restrict__ vol, const uint
                                     const uint64_t* __restrict__ ssq, uint32_t nlab, int ndim,
                                     float* __restrict__ mean_lt, float* __restrict__ shell_mean,
                                     float* __restrict__ sph, float* __restrict__ rnd,
-                                    const uint32_t* __restrict__ hist, float* __restrict__ hist_out) {
+                                    const uint32_t* __restrict__ hist, float* __restrict__ hist_out,
+                                    float vsize) {
     const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= nlab) return;
     const float nan = __int_as_float(0x7fc00000);
@@ -235,7 +236,7 @@ __global__ void closed_forms_kernel(const uint64_t* __restrict__ vol, const uint
         return;
     }
     const float a = (float)((double)sq[l] / SUM_SCALE / (double)V);
-    const float Vf = (float)V;
+    const float Vf = (float)V * vsize;            // physical volume (area): voxels x voxel size
     const float R = sqrtf((float)mx[l]);
     mean_lt[l] = a;
     const uint64_t ns = shc[l];
@@ -258,7 +259,7 @@ __global__ void closed_forms_kernel(const uint64_t* __restrict__ vol, const uint
         sph[l] = 2.0f * sqrtf(pi * Vf) / po;
     }
     if (hist_out) {
-        const float inv = 1.0f / Vf;
+        const float inv = 1.0f / (float)V;
         for (int k = 0; k < 32; ++k) hist_out[(size_t)l * 32 + k] = (float)hist[(size_t)l * 32 + k] * inv;
     }
 }
@@ -308,7 +309,7 @@ lt_status launch_measures_zero(lt_ctx* ctx, uint32_t max_label, const lt_measure
 template <typename L>
 static lt_status measures_finish_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
                                        uint32_t max_label, const lt_measures* out, void* scratch,
-                                       hipStream_t s) {
+                                       hipStream_t s, float vsize) {
     const size_t nlab = (size_t)max_label + 1;
     const MeasureScratch m = measure_scratch(scratch, nlab);
     if (out->hist32) {
@@ -326,7 +327,7 @@ static lt_status measures_finish_typed(lt_ctx* ctx, const L* lab, const Geom& g,
         ProfScope _p(ctx, s, "closed_forms");
         closed_forms_kernel<<<(unsigned)((nlab + 255) / 256), 256, 0, s>>>(
             out->volume, m.sq, out->max_lt_sq, out->shell_count, m.ssq, (uint32_t)nlab, g.ndim, out->mean_lt,
-            out->shell_mean_lt, out->sphericity, out->roundness, m.hist, out->hist32);
+            out->shell_mean_lt, out->sphericity, out->roundness, m.hist, out->hist32, vsize);
     }
     return hip_check(hipGetLastError(), "measures launch");
 }
@@ -334,7 +335,7 @@ static lt_status measures_finish_typed(lt_ctx* ctx, const L* lab, const Geom& g,
 template <typename L>
 static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* lt,
                                 uint32_t max_label, const lt_measures* out, void* scratch,
-                                hipStream_t s) {
+                                hipStream_t s, float vsize) {
     MeasureSums sums;
     lt_status st = launch_measures_zero(ctx, max_label, out, scratch, s, &sums);
     if (st) return st;
@@ -349,30 +350,33 @@ static lt_status measures_typed(lt_ctx* ctx, const L* lab, const Geom& g, const 
             object_sums<2, L><<<grid, blk, 0, s>>>(lab, lt, g.nx, g.ny, 1, max_label, sums.vol, sums.shc,
                                                    sums.mx, sums.sq, sums.ssq, ctx->d_err);
     }
-    return measures_finish_typed(ctx, lab, g, lt, max_label, out, scratch, s);
+    return measures_finish_typed(ctx, lab, g, lt, max_label, out, scratch, s, vsize);
 }
 
 lt_status launch_measures(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                           const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
-                          void* scratch, hipStream_t s) {
+                          void* scratch, hipStream_t s, float vsize) {
     switch (dt) {
-        case LT_U16: return measures_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s);
-        case LT_I32: return measures_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s);
-        case LT_U32: return measures_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s);
+        case LT_U16:
+            return measures_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s, vsize);
+        case LT_I32:
+            return measures_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s, vsize);
+        case LT_U32:
+            return measures_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s, vsize);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }
 
 lt_status launch_measures_finish(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                                  const int32_t* lt_sq, uint32_t max_label, const lt_measures* out,
-                                 void* scratch, hipStream_t s) {
+                                 void* scratch, hipStream_t s, float vsize) {
     switch (dt) {
         case LT_U16:
-            return measures_finish_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s);
+            return measures_finish_typed(ctx, (const uint16_t*)labels, g, lt_sq, max_label, out, scratch, s, vsize);
         case LT_I32:
-            return measures_finish_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s);
+            return measures_finish_typed(ctx, (const int32_t*)labels, g, lt_sq, max_label, out, scratch, s, vsize);
         case LT_U32:
-            return measures_finish_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s);
+            return measures_finish_typed(ctx, (const uint32_t*)labels, g, lt_sq, max_label, out, scratch, s, vsize);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }
@@ -383,7 +387,7 @@ lt_status launch_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q, 
                               float* roundness, hipStream_t s) {
     closed_forms_kernel<<<(n + 255) / 256, 256, 0, s>>>(volume, sum_lt_q, max_lt_sq, shell_count,
                                                         shell_sum_q, n, ndim, mean_lt, shell_mean_lt,
-                                                        sphericity, roundness, nullptr, nullptr);
+                                                        sphericity, roundness, nullptr, nullptr, 1.0f);
     return hip_check(hipGetLastError(), "closed forms launch");
 }
 

@@ -204,7 +204,10 @@ constexpr int PR_TY = 4, PR_ZB = 16, PR_W = 66, PR_H = PR_TY + 2, PR_TAB = 64;
 constexpr int PR_NT = PR_TY * 64;        // threads per block
 constexpr int PR_KS = PR_TY * 64 + 1;    // slice stride of the block's kept-field buffer (odd: no bank conflicts)
 
-template <typename L>
+// With W (anisotropic spacing) the table has one row per offset class (which of
+// z, y, x the offset moves along: 7 classes), since a weighted ball's containment
+// depends on the axes, not only on |o|^2.
+template <typename L, bool W = false>
 __global__ void __launch_bounds__(PR_NT)
 prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny, int nz,
         uint32_t max_label, const int32_t* __restrict__ tab, int32_t* __restrict__ kd,
@@ -268,7 +271,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         if (d > 0) {
             const L raw = lab[i];
             keep = true;
-            if (d <= PRUNE_DCAP) {
+            if (d <= PRUNE_DCAP && !W) {
                 const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d], a3 = tab[2 * (PRUNE_DCAP + 1) + d];
                 // largest D over the face, edge and corner neighbours: the centre is
                 // dropped when one class exceeds its table value
@@ -289,6 +292,23 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
                         }
                 }
                 keep = m1 <= a1 && m2 <= a2 && m3 <= a3;
+            } else if (d <= PRUNE_DCAP) {
+                // class c = 4 (dz != 0) + 2 (dy != 0) + (dx != 0) - 1
+                int mc[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int sl = (z + dz + 3) % 3;
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int c = 4 * (dz != 0) + 2 * (dy != 0) + (dx != 0) - 1;
+                            if (c < 0) continue;
+                            mc[c] = max(mc[c], s_d[sl][ty + 1 + dy][tx + 1 + dx]);
+                        }
+                }
+#pragma unroll
+                for (int c = 0; c < 7; ++c) keep &= mc[c] <= tab[c * (PRUNE_DCAP + 1) + d];
             }
             if (keep && d > (int)ZF_D_MASK) atomicOr(err, ERR_OVERFLOW);
             if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;   // flagged elsewhere
@@ -352,10 +372,12 @@ static size_t fronts3d_lds(int chunk) {
 // cost one test.  dq[i] holds the D of entry
 // 4 i + 3; the wave stops once no lane has maxb below it.  Members go to p, newest first, or with
 // SPILL to out[0..k).  Returns the front length k.
-template <bool SPILL>
+// With W the residual is v - wz (z - zc)^2: A = v - wz zc^2, t = A + 2 wz z zc and the
+// threshold maxb + wz z^2 (full 32-bit products).
+template <bool SPILL, bool W = false>
 __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int cnt4, int z, bool act,
-                                          uint32_t (&p)[ZF_PLANES], uint32_t* out) {
-    const int z2 = 2 * z, zsq = __mul24(z, z);
+                                          uint32_t (&p)[ZF_PLANES], uint32_t* out, int wz = 1) {
+    const int z2 = W ? 2 * wz * z : 2 * z, zsq = W ? wz * z * z : __mul24(z, z);
     int mz = act ? zsq : INT_MAX;
     int k = 0, lastv = 0;                 // front length, D of the last member
     bool more = true;                     // wave-uniform: a lane with maxb < D
@@ -366,13 +388,13 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
         const int A[4] = {(int)qa.y, (int)qa.w, (int)qb.y, (int)qb.w};
         int t[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) t[u] = __mul24(z2, zc[u]) + A[u];
+        for (int u = 0; u < 4; ++u) t[u] = (W ? z2 * zc[u] : __mul24(z2, zc[u])) + A[u];
         if (__ballot(max(max(t[0], t[1]), max(t[2], t[3])) > mz)) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const bool em = t[u] > mz;
                 if (__ballot(em)) {       // selects over the whole wave
-                    const int v = zc[u] * zc[u] + A[u];
+                    const int v = (W ? wz : 1) * zc[u] * zc[u] + A[u];
                     const bool app = em && lastv != v;
                     const uint32_t w = zf_pack(v, z - zc[u]);
                     if (SPILL) {
@@ -407,9 +429,11 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
 // is written whole to the block's spill region (second scan).  A list longer than
 // FZ_CAP, or a full spill region, marks the fronts "rescan" (count 7 without
 // ZF_SPILL): the paint pass then takes every centre of the column (same result).
+template <bool WG = false>
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
-         const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill) {
+         const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill,
+         int wz = 1) {
     extern __shared__ __align__(16) uint32_t S[];
     __shared__ int s_cm[64];
     __shared__ uint32_t s_used;                       // words of the block's spill region in use
@@ -441,7 +465,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             continue;
         }
         const size_t col = rowi + cx;
-        const int R = open_reach(cm);                 // no ball of the column reaches farther
+        const int R = WG ? open_reach_w(cm, wz) : open_reach(cm);   // no ball of the column reaches farther
         const int lo = max(0, c0 - R), hi = min(nz, c1 + R);
         int cnt = 0;
         const int32_t* kcol = kd + col * (size_t)nz;  // the column's kept field (column-major)
@@ -457,7 +481,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
                 // a centre listed only when its ball reaches a slice of the chunk
                 const int z = zb + 64 * u + lane;
                 const int d = max(max(c0 - z, z - (c1 - 1)), 0);
-                const bool keep = v[u] > __mul24(d, d);
+                const bool keep = v[u] > (WG ? wz * d * d : __mul24(d, d));
                 const unsigned long long m = __ballot(keep);
                 if (keep) {
                     const int pos = cnt + __popcll(m & below);
@@ -491,7 +515,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             const uint32_t e = h ? e1 : e0;
             const int r = h ? r1 : r0, zc = (int)(e & CL_Z_MASK), v = (int)(e >> CL_Z_BITS);
             if (lane + 64 * h < cnt) {
-                ent[r] = make_uint2((uint32_t)zc, (uint32_t)(v - zc * zc));
+                ent[r] = make_uint2((uint32_t)zc, (uint32_t)(v - (WG ? wz : 1) * zc * zc));
                 if ((r & 3) == 3) dq[r >> 2] = v;
             }
         }
@@ -507,7 +531,8 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             for (int h = 0; h < 2; ++h) {
                 const uint32_t e = h ? e1 : e0;       // order is free here
                 if (lane + 64 * h < cnt) {
-                    const int r = open_reach((int)(e >> CL_Z_BITS)), zc = (int)(e & CL_Z_MASK);
+                    const int ev = (int)(e >> CL_Z_BITS);
+                    const int r = WG ? open_reach_w(ev, wz) : open_reach(ev), zc = (int)(e & CL_Z_MASK);
                     const int a = max(zc - r, zr) - zr, b = min(zc + r, zr + 63) - zr;
                     if (a <= b) {
                         const int len = b - a + 1;
@@ -526,13 +551,13 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             uint32_t at = 0;
             bool fits = false;
             if (__ballot(live)) {
-                m = front_scan<false>((const uint4*)ent, dq, cnt4, z, live, p, nullptr);
+                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, wz);
                 if (m > ZF_PLANES) {
                     at = atomicAdd(&s_used, (uint32_t)m);
                     fits = at + (uint32_t)m <= cap;   // else: rescan instead
                 }
                 const bool again = m > ZF_PLANES && fits;   // second scan: the whole front to the spill
-                if (__ballot(again)) front_scan<true>((const uint4*)ent, dq, cnt4, z, again, p, region + at);
+                if (__ballot(again)) front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p, region + at, wz);
             }
             if (z < c1) {
                 uint32_t w0;
@@ -558,7 +583,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
 
 // One thread per pixel: background LT = 0, centre prune (8 neighbours), plane 0 =
 // D | bit 31 for kept centres (a kept pixel is its own disc), per-label maximum D.
-template <typename L>
+template <typename L, bool W = false>
 __global__ void __launch_bounds__(256)
 pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny,
          uint32_t max_label, const int32_t* __restrict__ tab, uint32_t* __restrict__ zf,
@@ -573,8 +598,9 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
         const L raw = lab[i];
         keep = true;
         if (d <= PRUNE_DCAP) {
-            const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d];
-            int m1 = 0, m2 = 0;                          // largest D of the edge / corner neighbours
+            // classes: unweighted by |o|^2 (edge, corner); with W by the axes moved
+            // along (c = 2 (dy != 0) + (dx != 0) - 1)
+            int mc[3] = {0, 0, 0};
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
@@ -583,10 +609,11 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
                     if (k == 0) continue;
                     const bool inb = y + dy >= 0 && y + dy < ny && x + dx >= 0 && x + dx < nx;
                     const int dn = inb ? D[(ptrdiff_t)i + (ptrdiff_t)dy * nx + dx] : 0;
-                    if (k == 1) m1 = max(m1, dn);
-                    else m2 = max(m2, dn);
+                    const int c = W ? 2 * (dy != 0) + (dx != 0) - 1 : k - 1;
+                    mc[c] = max(mc[c], dn);
                 }
-            keep = m1 <= a1 && m2 <= a2;
+            keep = mc[0] <= tab[d] && mc[1] <= tab[(PRUNE_DCAP + 1) + d];
+            if (W) keep = keep && mc[2] <= tab[2 * (PRUNE_DCAP + 1) + d];
         }
         zf[i] = keep ? ((uint32_t)d | 0x80000000u) : 0u;
         if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;
@@ -647,10 +674,22 @@ struct TileCtx {
     int lstride;           // words per level = H * TILE_STRIDE + 1 (the odd word staggers
                            // the levels over the LDS banks)
     unsigned long long* dirty;   // LDS mask of the tile rows painted in the current slice
+    int wy, wx;                  // squared spacings along y and x (anisotropic form)
 };
 
 __device__ __forceinline__ int reach_of(const TileCtx& t, int w) {
     return w < REACH_TAB ? (int)t.reach[w] : open_reach(w);
+}
+
+// Reach along y (rows a disc of residual b spans) and along x (half-width of the
+// interval of residual b on a row): the unit-spacing table, or the weighted reach.
+template <bool W>
+__device__ __forceinline__ int reach_y(const TileCtx& t, int b) {
+    return W ? open_reach_w(b, t.wy) : reach_of(t, b);
+}
+template <bool W>
+__device__ __forceinline__ int reach_x(const TileCtx& t, int b) {
+    return W ? open_reach_w(b, t.wx) : reach_of(t, b);
 }
 
 // Sparse-table update of one interval [xs, xe] (tile-relative, xs <= xe) of row
@@ -687,7 +726,7 @@ __device__ __forceinline__ void disc_unpack(const TileCtx& t, int w, int sy, int
     }
 }
 
-template <int NDIM>
+template <int NDIM, bool W>
 __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
     int* e_end = t.disc;
     int* e_v = t.disc + DL_CAP;
@@ -704,7 +743,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
         if (j < n) {
             int b, ro;
             disc_unpack<NDIM>(t, e_b[j], sy, b, ro);
-            const int h = reach_of(t, b);
+            const int h = reach_y<W>(t, b);
             dl[q] = max(-h, -ro);
             const int dhi = min(h, t.H - 1 - ro);
             cnt[q] = max(0, dhi - dl[q] + 1);
@@ -761,7 +800,7 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
             const int dy = j + (xw >> 12) - 16384;
             int b, ro;
             disc_unpack<NDIM>(t, e_b[o], sy, b, ro);
-            const int hw = reach_of(t, b - __mul24(dy, dy));
+            const int hw = reach_x<W>(t, b - (W ? t.wy * dy * dy : __mul24(dy, dy)));
             const int xs = max(pxr - hw, 0);
             const int xe = min(pxr + hw, t.W - 1);
             if (xs <= xe) paint_interval(t, ro + dy, xs, xe, (uint32_t)e_v[o]);
@@ -773,14 +812,14 @@ __device__ void disc_flush(const TileCtx& t, int n, int sy, int lane) {
 // Append the discs of the lanes with `has` (value v, squared radius b, centre
 // column sx) to the wave's list (n: wave-uniform length), painting the list first
 // when they would not fit.
-template <int NDIM>
+template <int NDIM, bool W>
 __device__ __forceinline__ void disc_push(const TileCtx& t, int& n, bool has, int v, int b, int sx, int sy,
                                           int lane) {
     const uint64_t m = __ballot(has);
     if (!m) return;
     const int k = __popcll(m);
     if (n + k > DL_CAP) {
-        disc_flush<NDIM>(t, n, sy, lane);
+        disc_flush<NDIM, W>(t, n, sy, lane);
         n = 0;
     }
     if (has) {
@@ -793,13 +832,17 @@ __device__ __forceinline__ void disc_push(const TileCtx& t, int& n, bool has, in
     n += k;
 }
 
-template <int NDIM, typename L>
+// With W (anisotropic spacing) the residual of a front entry is v - wz dz^2, discs
+// span the rows with wy dy^2 < b and intervals the columns with wx dx^2 < b - wy dy^2;
+// the fused shell test reads the face neighbours' labels (D = 1 identifies the
+// shell only at unit spacing).
+template <int NDIM, typename L, bool W = false>
 __global__ void __launch_bounds__(PAINT_THREADS)
 paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             const int32_t* __restrict__ kd, const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
             const uint32_t* __restrict__ toff, uint32_t nlab, int nx, int ny, int nz, int tile_y,
             uint32_t* __restrict__ counter, int32_t* __restrict__ lt, const uint32_t* __restrict__ spill,
-            int chunk, MeasureSums ms, const int32_t* __restrict__ Dmap) {
+            int chunk, MeasureSums ms, const int32_t* __restrict__ Dmap, Spacing spc = Spacing()) {
     // dynamic LDS: the sparse table [TILE_LEVELS][tile_y][TILE_STRIDE], then one disc
     // list per wave
     extern __shared__ uint32_t M[];
@@ -844,7 +887,11 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int z0 = bb[0 * nlab + l], z1 = bb[1 * nlab + l] + 1;
         const int y0 = bb[2 * nlab + l], y1 = bb[3 * nlab + l] + 1;
         const int x0 = bb[4 * nlab + l], x1 = bb[5 * nlab + l] + 1;
-        const int R = open_reach(max(maxd[l], 1));
+        const int mdl = max(maxd[l], 1);
+        const int R = W ? 0 : open_reach(mdl);
+        const int Rz = W ? open_reach_w(mdl, spc.wz) : R;     // reach of the object's balls per axis
+        const int Ry = W ? open_reach_w(mdl, spc.wy) : R;
+        const int Rx = W ? open_reach_w(mdl, spc.wx) : R;
         const int tiles_x = (x1 - x0 + TILE_X - 1) / TILE_X;
         const int tt = (int)(item - toff[l]);
         TileCtx t;
@@ -856,8 +903,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         t.H = min(tile_y, y1 - t.ty0);
         t.W = min(TILE_X, x1 - t.tx0);
         t.lstride = t.H * TILE_STRIDE + 1;
-        const int sy0 = max(y0, t.ty0 - R), sy1 = min(y1, t.ty0 + t.H + R);
-        const int sx0 = max(x0, t.tx0 - R), sx1 = min(x1, t.tx0 + t.W + R);
+        t.wy = spc.wy;
+        t.wx = spc.wx;
+        const int sy0 = max(y0, t.ty0 - Ry), sy1 = min(y1, t.ty0 + t.H + Ry);
+        const int sx0 = max(x0, t.tx0 - Rx), sx1 = min(x1, t.tx0 + t.W + Rx);
         // fused measures: this thread's share of the item's volume, radius sums,
         // largest LT and shell terms (every painted cell is a voxel of label l)
         uint32_t a_n = 0, a_sn = 0;
@@ -942,10 +991,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                             } else {
                                 v = (int)(e[p] & ZF_D_MASK);
                                 const int dz = (int)((e[p] >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
-                                b = v - dz * dz;
+                                b = v - (W ? spc.wz : 1) * dz * dz;
                             }
                         }
-                        disc_push<NDIM>(t, nlist, has, v, b, sx, sy, lane);
+                        disc_push<NDIM, W>(t, nlist, has, v, b, sx, sy, lane);
                     }
                     // long fronts kept in the front pass's spill region
                     if (NDIM == 3 && __ballot(spilled)) {
@@ -963,9 +1012,9 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                                 const uint32_t w = sp[q];
                                 v = (int)(w & ZF_D_MASK);
                                 const int dz = (int)((w >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
-                                b = v - dz * dz;
+                                b = v - (W ? spc.wz : 1) * dz * dz;
                             }
-                            disc_push<NDIM>(t, nlist, has, v, b, sx, sy, lane);
+                            disc_push<NDIM, W>(t, nlist, has, v, b, sx, sy, lane);
                         }
                     }
                     // fronts that did not fit the spill region: every kept centre of the
@@ -974,28 +1023,28 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     // together, four independent loads at a time.
                     if (NDIM == 3 && __ballot(rescan)) {
                         const size_t col = (size_t)sy * nx + sx;
-                        for (int d0 = -R; d0 <= R; d0 += 4) {
+                        for (int d0 = -Rz; d0 <= Rz; d0 += 4) {
                             int kv[4];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int zc = pz + d0 + u;
-                                kv[u] = (rescan && d0 + u <= R && zc >= z0 && zc < z1) ? kd[col * (size_t)nz + zc] : 0;
+                                kv[u] = (rescan && d0 + u <= Rz && zc >= z0 && zc < z1) ? kd[col * (size_t)nz + zc] : 0;
                             }
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int dz = d0 + u;
-                                const int b = kv[u] - dz * dz;
-                                disc_push<NDIM>(t, nlist, kv[u] > 0 && b > 0, kv[u], b, sx, sy, lane);
+                                const int b = kv[u] - (W ? spc.wz : 1) * dz * dz;
+                                disc_push<NDIM, W>(t, nlist, kv[u] > 0 && b > 0, kv[u], b, sx, sy, lane);
                             }
                         }
                     }
                 }
                 if (NDIM == 2 && nlist) {                 // 2D lists hold one source row
-                    disc_flush<NDIM>(t, nlist, sy, lane);
+                    disc_flush<NDIM, W>(t, nlist, sy, lane);
                     nlist = 0;
                 }
             }
-            if (nlist) disc_flush<NDIM>(t, nlist, sylast, lane);
+            if (nlist) disc_flush<NDIM, W>(t, nlist, sylast, lane);
             __syncthreads();
             // push-down of the sparse table, one wave per painted row: level k-1 at
             // column c takes the blocks of level k starting at c and c - 2^(k-1); then
@@ -1026,8 +1075,19 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                             const int v = (int)val[0];
                             const uint64_t q = radius_q23(v);
                             // on the shell exactly when a face neighbour (or the image
-                            // border) is not of the object: D = 1
-                            const bool shell = Dmap[gi] == 1;
+                            // border) is not of the object: D = 1 at unit spacing
+                            bool shell;
+                            if (!W) {
+                                shell = Dmap[gi] == 1;
+                            } else {
+                                const L lo = (L)l;
+                                shell = gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1 || lab[gi - 1] != lo ||
+                                        lab[gi + 1] != lo || lab[gi - nx] != lo || lab[gi + nx] != lo;
+                                if (NDIM == 3 && !shell) {
+                                    const size_t pl = (size_t)nx * ny;
+                                    shell = pz == 0 || pz == nz - 1 || lab[gi - pl] != lo || lab[gi + pl] != lo;
+                                }
+                            }
                             ++a_n;
                             a_q += q;
                             a_mx = max(a_mx, v);
@@ -1118,7 +1178,10 @@ int paint_tile_rows(lt_ctx* ctx) {
     std::call_once(once, [] {
         const void* fns[] = {(const void*)paint_tiles<3, uint16_t>, (const void*)paint_tiles<3, int32_t>,
                              (const void*)paint_tiles<3, uint32_t>, (const void*)paint_tiles<2, uint16_t>,
-                             (const void*)paint_tiles<2, int32_t>, (const void*)paint_tiles<2, uint32_t>};
+                             (const void*)paint_tiles<2, int32_t>, (const void*)paint_tiles<2, uint32_t>,
+                             (const void*)paint_tiles<3, uint16_t, true>, (const void*)paint_tiles<3, int32_t, true>,
+                             (const void*)paint_tiles<3, uint32_t, true>, (const void*)paint_tiles<2, uint16_t, true>,
+                             (const void*)paint_tiles<2, int32_t, true>, (const void*)paint_tiles<2, uint32_t, true>};
         for (const void* f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PAINT_DYN64);
     });
@@ -1131,7 +1194,13 @@ int paint_tile_rows(lt_ctx* ctx) {
 template <typename L>
 static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const int32_t* D,
                                  uint32_t max_label, int32_t* lt, void* scratch, hipStream_t s,
-                                 const MeasureSums* sums, int32_t* boxes) {
+                                 const MeasureSums* sums, int32_t* boxes, const Spacing& sp) {
+    const bool w = !sp.unit();
+    const int32_t* tabw = nullptr;                    // weighted containment tables
+    if (w) {
+        lt_status st = prune_tables_weighted(ctx, g.ndim, sp, &tabw);
+        if (st) return st;
+    }
     const MeasureSums none{nullptr, nullptr, nullptr, nullptr, nullptr};
     const MeasureSums ms = sums ? *sums : none;
     const ThickLayout lay = thick_layout(g, max_label);
@@ -1163,19 +1232,31 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     if (g.ndim == 3) {
         {
             ProfScope _p(ctx, s, "prune3d");
-            prune3d<L><<<dim3((g.nx + 63) / 64, (g.ny + PR_TY - 1) / PR_TY, (g.nz + PR_ZB - 1) / PR_ZB),
-                          dim3(64, PR_TY), 0, s>>>(
-                lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd, lt, maxd, colmax, ctx->d_err);
+            const dim3 grid((g.nx + 63) / 64, (g.ny + PR_TY - 1) / PR_TY, (g.nz + PR_ZB - 1) / PR_ZB);
+            if (w)
+                prune3d<L, true><<<grid, dim3(64, PR_TY), 0, s>>>(lab, D, g.nx, g.ny, g.nz, max_label, tabw, kd, lt,
+                                                                   maxd, colmax, ctx->d_err);
+            else
+                prune3d<L><<<grid, dim3(64, PR_TY), 0, s>>>(lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd,
+                                                             lt, maxd, colmax, ctx->d_err);
         }
         {
             ProfScope _p(ctx, s, "fronts3d");
-            fronts3d<<<dim3((g.nx + 63) / 64, g.ny, (g.nz + chunk - 1) / chunk), 256, fronts3d_lds(chunk), s>>>(
-                kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill);
+            const dim3 grid((g.nx + 63) / 64, g.ny, (g.nz + chunk - 1) / chunk);
+            if (w)
+                fronts3d<true><<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill,
+                                                                      sp.wz);
+            else
+                fronts3d<<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill);
         }
     } else {
         ProfScope _p(ctx, s, "pixels2d");
-        pixels2d<L><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(
-            lab, D, g.nx, g.ny, max_label, ctx->d_prune2, zf, lt, maxd);
+        if (w)
+            pixels2d<L, true><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(lab, D, g.nx, g.ny, max_label,
+                                                                                  tabw, zf, lt, maxd);
+        else
+            pixels2d<L><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(lab, D, g.nx, g.ny, max_label,
+                                                                            ctx->d_prune2, zf, lt, maxd);
     }
     const int tile_y = paint_tile_rows(ctx);
     {
@@ -1191,9 +1272,16 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     const int blocks = ctx->n_cu * (two ? 2 : 1);
     {
         ProfScope _p(ctx, s, "paint_tiles");
-        if (g.ndim == 3)
+        if (g.ndim == 3 && w)
+            paint_tiles<3, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
+                                                                     g.nz, tile_y, counter, lt, spill, chunk, ms, D,
+                                                                     sp);
+        else if (g.ndim == 3)
             paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
                                                                g.nz, tile_y, counter, lt, spill, chunk, ms, D);
+        else if (w)
+            paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
+                                                                     tile_y, counter, lt, spill, chunk, ms, D, sp);
         else
             paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
                                                                tile_y, counter, lt, spill, chunk, ms, D);
@@ -1203,17 +1291,20 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
 
 lt_status launch_thickness(lt_ctx* ctx, const void* labels, lt_dtype dt, const Geom& g,
                            const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
-                           void* scratch, hipStream_t s, const MeasureSums* sums, int32_t* boxes) {
+                           void* scratch, hipStream_t s, const MeasureSums* sums, int32_t* boxes,
+                           const Spacing* sp) {
+    const Spacing unit;
+    const Spacing& spc = sp ? *sp : unit;
     switch (dt) {
         case LT_U16:
             return thickness_typed(ctx, (const uint16_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums,
-                                   boxes);
+                                   boxes, spc);
         case LT_I32:
             return thickness_typed(ctx, (const int32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums,
-                                   boxes);
+                                   boxes, spc);
         case LT_U32:
             return thickness_typed(ctx, (const uint32_t*)labels, g, dist_sq, max_label, lt_sq, scratch, s, sums,
-                                   boxes);
+                                   boxes, spc);
     }
     return set_error(LT_E_DTYPE, "unknown dtype");
 }

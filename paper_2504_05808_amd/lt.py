@@ -72,6 +72,11 @@ def load():
     lib.lt_pipeline_static_bytes.restype = ctypes.c_size_t
     lib.lt_closed_forms.argtypes = [P, P, P, P, P, U32, I, P, P, P, P, V]
     lib.lt_mesh_measures.argtypes = [P, P, I, I, i64p, U32, P, P, P, V]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.lt_edt_aniso.argtypes = [P, P, I, I, i64p, i32p, P, V]
+    lib.lt_thickness_aniso.argtypes = [P, P, I, I, i64p, i32p, P, U32, P, V]
+    lib.lt_object_measures_aniso.argtypes = [P, P, I, I, i64p, i32p, P, U32, ctypes.POINTER(_Measures), V]
+    lib.lt_pipeline_aniso.argtypes = [P, P, I, I, i64p, i32p, U32, P, P, ctypes.POINTER(_Measures), V]
     lib.lt_filtered_roundness.argtypes = [P, P, I, I, i64p, P, P, U32, I, P, V]
     lib.lt_remap_roundness.argtypes = [P, P, U32, ctypes.c_float, P, V]
     lib.lt_sync_status.argtypes = [P, V]
@@ -92,7 +97,8 @@ def load():
     lib.lt_last_error.restype = ctypes.c_char_p
     lib.lt_version.restype = ctypes.c_char_p
     for f in ("lt_ctx_create", "lt_ctx_destroy", "lt_edt", "lt_thickness", "lt_object_measures", "lt_pipeline",
-              "lt_pipeline_static", "lt_mesh_measures", "lt_filtered_roundness", "lt_remap_roundness",
+              "lt_pipeline_static", "lt_mesh_measures", "lt_edt_aniso", "lt_thickness_aniso",
+              "lt_object_measures_aniso", "lt_pipeline_aniso", "lt_filtered_roundness", "lt_remap_roundness",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
               "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
               "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
@@ -375,6 +381,49 @@ def remap_roundness(roundness: torch.Tensor, r_min: float | None = None, out: to
     _check(ctx._lib.lt_remap_roundness(ctx.handle, _ptr(r), r.numel(), ctypes.c_float(m), _ptr(out),
                                        _stream(stream)))
     return out
+
+
+def _spacing(sq_spacing, ndim: int):
+    w = [int(v) for v in sq_spacing]
+    if len(w) != ndim:
+        raise ValueError(f"sq_spacing needs {ndim} entries (got {len(w)})")
+    return (ctypes.c_int32 * ndim)(*w)
+
+
+def measure_aniso(labels: torch.Tensor, max_label: int, sq_spacing, ctx: Context | None = None, stream=None):
+    """Anisotropic spacing, three calls (lt_edt_aniso, lt_thickness_aniso,
+    lt_object_measures_aniso): (dist_sq, lt_sq, Measures)."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    w = _spacing(sq_spacing, lab.dim())
+    d = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+    t = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+    m = alloc_measures(int(max_label) + 1, lab.device)
+    _check(ctx._lib.lt_edt_aniso(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), w, _ptr(d), _stream(stream)))
+    _check(ctx._lib.lt_thickness_aniso(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), w, _ptr(d),
+                                       int(max_label), _ptr(t), _stream(stream)))
+    ms = _measures_struct(m)
+    _check(ctx._lib.lt_object_measures_aniso(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), w, _ptr(t),
+                                             int(max_label), ctypes.byref(ms), _stream(stream)))
+    return d, t, m
+
+
+def pipeline_aniso(labels: torch.Tensor, max_label: int, sq_spacing, out=None, ctx: Context | None = None,
+                   stream=None):
+    """Anisotropic spacing in one call (lt_pipeline_aniso): (dist_sq, lt_sq, Measures)."""
+    lab, dt = _labels(labels)
+    ctx = ctx or default_context()
+    w = _spacing(sq_spacing, lab.dim())
+    if out is None:
+        d = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+        t = torch.empty(lab.shape, dtype=torch.int32, device=lab.device)
+        m = alloc_measures(int(max_label) + 1, lab.device)
+    else:
+        d, t, m = out
+    ms = _measures_struct(m)
+    _check(ctx._lib.lt_pipeline_aniso(ctx.handle, _ptr(lab), dt, lab.dim(), _shape(lab), w, int(max_label),
+                                      _ptr(d), _ptr(t), ctypes.byref(ms), _stream(stream)))
+    return d, t, m
 
 
 def version() -> str:

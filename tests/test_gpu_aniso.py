@@ -1,0 +1,186 @@
+"""GPU parity of the anisotropic-spacing calls (lt_edt_aniso, lt_thickness_aniso,
+lt_object_measures_aniso, lt_pipeline_aniso) against the weighted oracle.
+
+Distances and local thickness are weighted squared lengths (exact integers) and
+compared bit-exactly; counts exactly; the FP32 measures within 1e-5 relative of the
+FP64 oracle.  Cross-checks against the plain path: unit weights give the plain
+calls' results bit for bit, and weights (k, k, k) give exactly k times the plain
+D and LT (every squared length scales by k)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lt_oracle as O
+from paper_2504_05808_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+FLOAT_KEYS = ("mean_lt", "shell_mean_lt", "sphericity", "roundness")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_05808_amd import lt
+    lt.load()
+    return torch, lt
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _host(d, t, m):
+    out = dict(dist_sq=d.cpu().numpy().astype(np.int64), lt_sq=t.cpu().numpy().astype(np.int64))
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        out[k] = getattr(m, k).cpu().numpy().astype(np.int64)
+    for k in FLOAT_KEYS:
+        out[k] = getattr(m, k).cpu().numpy().astype(np.float64)
+    return out
+
+
+def run_aniso(gpu, lab, w, max_label=None):
+    """Both forms; they must agree bit for bit."""
+    torch, lt = gpu
+    max_label = int(lab.max()) if max_label is None else max_label
+    t = torch.from_numpy(np.ascontiguousarray(lab)).cuda()
+    a = _host(*lt.measure_aniso(t, max_label, w))
+    b = _host(*lt.pipeline_aniso(t, max_label, w))
+    lt.default_context().sync_status()
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=f"fused vs separate: {k}")
+    return a
+
+
+def compare(got, ref, fields=True):
+    if fields:
+        np.testing.assert_array_equal(got["dist_sq"], ref["dist_sq"])
+        np.testing.assert_array_equal(got["lt_sq"], ref["lt_sq"])
+    n = len(ref["volume"])
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        np.testing.assert_array_equal(got[k][:n], ref[k])
+    ok = ref["volume"] > 0
+    for k in FLOAT_KEYS:
+        g, r = got[k][:n], ref[k]
+        assert np.all(np.isnan(g[~ok]))
+        okk = ok & ~np.isnan(r)
+        np.testing.assert_allclose(g[okk], r[okk], rtol=RTOL, atol=0, err_msg=k)
+
+
+W3 = [(4, 1, 1), (1, 9, 4), (2, 3, 5), (1, 1, 16)]
+W2 = [(4, 1), (1, 9), (3, 5)]
+SHAPES3 = [(3, 5, 7), (9, 130, 67), (17, 33, 65), (40, 9, 77), (1, 50, 60), (45, 1, 1)]
+SHAPES2 = [(1, 37), (23, 1), (37, 70), (130, 67)]
+
+
+@pytest.mark.parametrize("shape", SHAPES3 + SHAPES2)
+@pytest.mark.parametrize("dtype", [np.uint16, np.int32, np.uint32])
+def test_random_labels_bit_exact(gpu, shape, dtype):
+    rng = synth.rng_for(6000 + len(shape) * 100 + shape[-1])
+    for i, (blob, nl, pbg) in enumerate([(1, 3, 0.3), (4, 5, 0.1), (8, 2, 0.0)]):
+        lab = synth.random_labels(rng, shape, n_labels=nl, p_bg=pbg, blob=blob, dtype=dtype)
+        ws = W3 if len(shape) == 3 else W2
+        w = ws[i % len(ws)]
+        _note(f"aniso random shape={shape} dtype={np.dtype(dtype).name} blob={blob} w={w}")
+        ref = O.measure(lab, per_object=False, weights=w)
+        compare(run_aniso(gpu, lab, w), ref)
+
+
+def test_scaled_unit_weights_against_the_plain_path(gpu):
+    """Weights (k, k, k) through the weighted kernels = k x the plain path; unit
+    weights = the plain path, bit for bit."""
+    torch, lt = gpu
+    lab, _ = synth.cfg2()
+    max_label = int(lab.max())
+    t = torch.from_numpy(lab).cuda()
+    plain = _host(*lt.pipeline(t, max_label))
+    unit = run_aniso(gpu, lab, (1, 1, 1))
+    for k in plain:
+        np.testing.assert_array_equal(unit[k], plain[k], err_msg=k)
+    for k in (2, 3):
+        got = run_aniso(gpu, lab, (k, k, k))
+        np.testing.assert_array_equal(got["dist_sq"], k * plain["dist_sq"])
+        np.testing.assert_array_equal(got["lt_sq"], k * plain["lt_sq"])
+        ok = plain["volume"] > 0
+        # radii scale by sqrt(k) and so does every length: sphericity and roundness unchanged
+        for key in ("sphericity", "roundness"):
+            np.testing.assert_allclose(got[key][ok], plain[key][ok], rtol=2e-6)
+    lab2, _ = synth.cfg1()
+    t2 = torch.from_numpy(lab2).cuda()
+    plain2 = _host(*lt.pipeline(t2, int(lab2.max())))
+    got2 = run_aniso(gpu, lab2, (3, 3))
+    np.testing.assert_array_equal(got2["lt_sq"], 3 * plain2["lt_sq"])
+
+
+def _weighted_ball(weights, R):
+    half = [int(math.isqrt(R // w)) for w in weights]
+    grids = np.meshgrid(*[np.arange(-h - 1, h + 2) for h in half], indexing="ij")
+    n2 = sum(w * g * g for w, g in zip(weights, grids))
+    return n2 <= R, min(int(v) for v in n2.ravel() if v > R)
+
+
+@pytest.mark.parametrize("weights,R", [((4, 1, 1), 3000), ((1, 4, 9), 2500), ((9, 1, 1), 12000),
+                                       ((4, 1), 40000), ((1, 16), 30000)])
+def test_large_weighted_balls(gpu, weights, R):
+    """Weighted balls wide enough to span several paint tiles and to give long
+    z-fronts (rescans and spills): LT equals the centre's D everywhere."""
+    m, above = _weighted_ball(weights, R)
+    lab = m.astype(np.int32)
+    _note(f"aniso ball w={weights} R={R} shape={lab.shape}")
+    got = run_aniso(gpu, lab, weights)
+    assert got["dist_sq"].max() == above
+    assert np.all(got["lt_sq"][m] == above) and np.all(got["lt_sq"][~m] == 0)
+    assert got["roundness"][1] == pytest.approx(1.0, abs=1e-6)
+    assert got["sphericity"][1] > 0.999
+
+
+def test_cfg2_ellipsoids(gpu):
+    lab, _ = synth.cfg2()
+    for w in ((4, 1, 1), (1, 2, 3)):
+        _note(f"aniso cfg2 w={w}")
+        ref = O.measure(lab, weights=w)
+        compare(run_aniso(gpu, lab, w), ref)
+
+
+def test_512cube_every_second_slice(gpu):
+    """The 512^3 benchmark volume sampled every second slice: a 256 x 512 x 512
+    volume of slices twice as thick as the pixels (squared spacings 4, 1, 1);
+    every object against the oracle."""
+    torch, lt = gpu
+    vol, meta = synth.cfg3()
+    lab = np.ascontiguousarray(vol[::2])
+    w = (4, 1, 1)
+    max_label = int(lab.max())
+    _note(f"aniso 256x512x512 w={w}")
+    t = torch.from_numpy(lab).cuda()
+    got = _host(*lt.pipeline_aniso(t, max_label, w))
+    lt.default_context().sync_status()
+    D, LT, _ = O.fields(lab, threads=16, weights=w)
+    np.testing.assert_array_equal(got["dist_sq"], D)
+    np.testing.assert_array_equal(got["lt_sq"], LT)
+    sums = O.object_sums(lab, LT, max_label)
+    ref = dict(sums)
+    ref.update(O.closed_forms(sums, 3, voxel_size=2.0))
+    compare(got, ref, fields=False)
+    # repeat run, bitwise
+    again = _host(*lt.pipeline_aniso(t, max_label, w))
+    for k in ("dist_sq", "lt_sq", "volume", "sphericity", "roundness"):
+        np.testing.assert_array_equal(again[k], got[k])
+
+
+def test_argument_errors(gpu):
+    torch, lt = gpu
+    t = torch.zeros((8, 9, 10), dtype=torch.int32, device="cuda")
+    for w in ((0, 1, 1), (1, 256, 1), (1, 1)):
+        with pytest.raises((lt.LTError, ValueError)):
+            lt.pipeline_aniso(t, 3, w)
+    big = torch.zeros((1024, 1024, 1024), dtype=torch.uint16, device="cuda")
+    with pytest.raises(lt.LTError) as e:       # squared distances could reach 255 x 512^2
+        lt.pipeline_aniso(big, 3, (255, 255, 255))
+    assert e.value.status == 1
