@@ -44,7 +44,9 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* Status codes (int32_t, so that any value crossing the interface is well defined). */
+typedef int32_t lt_status;
+enum {
     LT_OK = 0,
     LT_E_ARG = 1,          /* null pointer or invalid argument */
     LT_E_DTYPE = 2,        /* unknown label dtype */
@@ -55,9 +57,11 @@ typedef enum {
     LT_E_OVERFLOW = 7,     /* device: an intermediate exceeded its range */
     LT_E_WORKSPACE = 8,    /* a caller-provided buffer is too small */
     LT_E_NOT_READY = 9     /* object not initialised (e.g. model not trained) */
-} lt_status;
+};
 
-typedef enum { LT_U16 = 1, LT_I32 = 2, LT_U32 = 3 } lt_dtype;
+/* Label element types (int32_t: unknown values are rejected with LT_E_DTYPE). */
+typedef int32_t lt_dtype;
+enum { LT_U16 = 1, LT_I32 = 2, LT_U32 = 3 };
 
 typedef struct lt_ctx lt_ctx;
 
@@ -274,7 +278,8 @@ lt_status lt_sync_status(lt_ctx* ctx, void* stream);
  * first; the whole batch is captured once into a hipGraph that lt_batch_run
  * replays with a single hipGraphLaunch on `stream`.  The batch owns its scratch
  * (one region per lane); the caller keeps every volume's buffers alive and at the
- * same addresses for the life of the batch.  Replays of one batch must not overlap. */
+ * same addresses for the life of the batch.  Replays of one batch must not overlap.
+ * Errors found on the device are reported per volume by lt_batch_status. */
 typedef struct {
     const void* labels;       /* device, `dtype` of the batch */
     int ndim;                 /* 2 or 3 */
@@ -288,6 +293,12 @@ typedef struct lt_batch lt_batch;
 lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n_volumes, lt_dtype dtype,
                           lt_batch** out);
 lt_status lt_batch_run(lt_batch* batch, void* stream);
+/* Per-volume status of the batch's replays so far: synchronise `stream`, read and
+ * clear every volume's device error word (device-detected errors of a batch go to
+ * these words, not to the context's).  status: optional HOST array of n_volumes
+ * entries, each LT_OK, LT_E_LABEL_RANGE or LT_E_OVERFLOW; a bad volume leaves the
+ * others' entries (and outputs) intact.  Returns the first volume's error, or LT_OK. */
+lt_status lt_batch_status(lt_batch* batch, void* stream, int32_t* status);
 lt_status lt_batch_destroy(lt_batch* batch);
 
 /* ---------------------------------------------------------------- tuning

@@ -3,10 +3,12 @@
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "lt_internal.h"
@@ -30,6 +32,35 @@ lt_status hip_check(hipError_t e, const char* what) {
     return set_error(LT_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Allocation fault injection (tests of the failure paths): LT_FAULT_INJECT=alloc makes
+// every device allocation of the library fail with LT_E_ALLOC; alloc:N lets N more
+// allocations succeed first (counted from when that value was first seen).
+static std::mutex g_fault_mu;
+static std::string g_fault_seen;
+static long g_fault_left = -1;                  // allocations still allowed; -1: no injection
+
+static bool fault_alloc_next(bool consume) {
+    std::lock_guard<std::mutex> lock(g_fault_mu);
+    const char* e = getenv("LT_FAULT_INJECT");
+    const std::string v = e ? e : "";
+    if (v != g_fault_seen) {
+        g_fault_seen = v;
+        g_fault_left = -1;
+        if (v == "alloc") g_fault_left = 0;
+        else if (v.rfind("alloc:", 0) == 0) g_fault_left = strtol(v.c_str() + 6, nullptr, 10);
+    }
+    if (g_fault_left < 0) return false;
+    if (g_fault_left == 0) return true;
+    if (consume) --g_fault_left;
+    return false;
+}
+
+lt_status device_alloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (fault_alloc_next(true)) return set_error(LT_E_ALLOC, "%s: injected allocation failure (LT_FAULT_INJECT)", what);
+    return hip_check(hipMalloc(p, bytes), what);
+}
+
 lt_status ensure_scratch(lt_ctx* ctx, size_t bytes) {
     if (bytes <= ctx->scratch.bytes) return LT_OK;
     if (ctx->scratch.ptr) {
@@ -41,7 +72,7 @@ lt_status ensure_scratch(lt_ctx* ctx, size_t bytes) {
     }
     size_t want = bytes + bytes / 8 + (1u << 20);
     void* p = nullptr;
-    lt_status st = hip_check(hipMalloc(&p, want), "hipMalloc(scratch)");
+    lt_status st = device_alloc(&p, want, "hipMalloc(scratch)");
     if (st) return st;
     ctx->scratch.ptr = p;
     ctx->scratch.bytes = want;
@@ -187,7 +218,7 @@ lt_status prune_tables_weighted(lt_ctx* ctx, int ndim, const Spacing& sp, const 
     build_prune_tables_weighted(ndim, sp, tab);
     int32_t* d = nullptr;
     const size_t bytes = tab.size() * sizeof(int32_t);
-    lt_status st = hip_check(hipMalloc((void**)&d, bytes), "hipMalloc(weighted prune tables)");
+    lt_status st = device_alloc((void**)&d, bytes, "hipMalloc(weighted prune tables)");
     if (st) return st;
     if ((st = hip_check(hipMemcpy(d, tab.data(), bytes, hipMemcpyHostToDevice), "copy weighted prune tables"))) {
         (void)hipFree(d);
@@ -285,6 +316,10 @@ const char* lt_status_str(lt_status s) {
 lt_status lt_ctx_create(lt_ctx** out, int device) {
     if (!out) return set_error(LT_E_ARG, "out is NULL");
     *out = nullptr;
+    // a context needs device memory: with allocations failing by injection it fails
+    // before touching the device
+    if (fault_alloc_next(false))
+        return set_error(LT_E_ALLOC, "lt_ctx_create: injected allocation failure (LT_FAULT_INJECT)");
     int count = 0;
     lt_status st = hip_check(hipGetDeviceCount(&count), "hipGetDeviceCount");
     if (st) return st;
@@ -307,9 +342,9 @@ lt_status lt_ctx_create(lt_ctx** out, int device) {
         build_prune_tables(2, g_tab2);
     });
     size_t b3 = g_tab3.size() * sizeof(int32_t), b2 = g_tab2.size() * sizeof(int32_t);
-    if ((st = hip_check(hipMalloc((void**)&c->d_err, sizeof(uint32_t)), "hipMalloc(err)")) ||
-        (st = hip_check(hipMalloc((void**)&c->d_prune3, b3), "hipMalloc(tab3)")) ||
-        (st = hip_check(hipMalloc((void**)&c->d_prune2, b2), "hipMalloc(tab2)")) ||
+    if ((st = device_alloc((void**)&c->d_err, sizeof(uint32_t), "hipMalloc(err)")) ||
+        (st = device_alloc((void**)&c->d_prune3, b3, "hipMalloc(tab3)")) ||
+        (st = device_alloc((void**)&c->d_prune2, b2, "hipMalloc(tab2)")) ||
         (st = hip_check(hipMemcpy(c->d_prune3, g_tab3.data(), b3, hipMemcpyHostToDevice), "copy tab3")) ||
         (st = hip_check(hipMemcpy(c->d_prune2, g_tab2.data(), b2, hipMemcpyHostToDevice), "copy tab2")) ||
         (st = hip_check(hipMemset(c->d_err, 0, sizeof(uint32_t)), "clear err")) ||

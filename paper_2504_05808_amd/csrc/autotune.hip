@@ -128,7 +128,7 @@ lt_status lt_autotune(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
     void* buf = nullptr;
     const size_t fields = 2 * g.n * sizeof(int32_t);
     const size_t per = 2 * sizeof(uint64_t) + sizeof(int32_t) + 4 * sizeof(float);
-    if ((st = hip_check(hipMalloc(&buf, fields + nlab * per + 1024), "hipMalloc(autotune)"))) return st;
+    if ((st = device_alloc(&buf, fields + nlab * per + 1024, "hipMalloc(autotune)"))) return st;
     char* p = (char*)buf;
     int32_t* dist = (int32_t*)p;
     int32_t* ltq = (int32_t*)(p + g.n * sizeof(int32_t));

@@ -6,7 +6,9 @@
 // and captures the whole pipeline of every volume into one hipGraph: the lanes fork
 // from and join back into one origin stream, so independent volumes may run
 // concurrently.  lt_batch_run replays it with a single hipGraphLaunch.  The graph
-// holds kernel nodes only (no memset or allocation nodes).
+// holds kernel nodes only (no memset or allocation nodes).  Each volume's kernels
+// record device-detected errors in that volume's own error word, so one bad volume
+// is reported as such and does not mark the others (lt_batch_status).
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -20,6 +22,7 @@
 struct lt_batch {
     lt_ctx* ctx = nullptr;
     void* scratch = nullptr;
+    uint32_t* d_status = nullptr;       // one device error word per volume
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int n = 0;
@@ -115,8 +118,11 @@ lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n, lt_dtype dt
     b->ctx = ctx;
     b->n = n;
     b->lanes = lanes;
-    if (total > 0 && (st = hip_check(hipMalloc(&b->scratch, total), "hipMalloc(batch scratch)"))) {
-        delete b;
+    if ((total > 0 && (st = device_alloc(&b->scratch, total, "hipMalloc(batch scratch)"))) ||
+        (st = device_alloc((void**)&b->d_status, (size_t)std::max(n, 1) * sizeof(uint32_t),
+                           "hipMalloc(batch status)")) ||
+        (st = hip_check(hipMemset(b->d_status, 0, (size_t)std::max(n, 1) * sizeof(uint32_t)), "clear batch status"))) {
+        lt_batch_destroy(b);
         return st;
     }
     (void)paint_tile_rows(ctx);                 // one-time kernel attributes, outside capture
@@ -156,9 +162,14 @@ lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n, lt_dtype dt
     for (int k = 0; k < lanes; ++k) {
         if ((st = hip_check(hipStreamWaitEvent(ls[k], ev[lanes], 0), "fork wait"))) return fail(st);
         void* scr = (char*)b->scratch + lane_off[k];
-        for (int i : lane_vols[k])
-            if (geo[i].n > 0 && (st = launch_volume(ctx, vols[i], dtype, geo[i], scr, ls[k])))
-                return fail(st);
+        for (int i : lane_vols[k]) {
+            // the volume's kernels take its own error word while they are captured
+            uint32_t* ctx_err = ctx->d_err;
+            ctx->d_err = b->d_status + i;
+            if (geo[i].n > 0) st = launch_volume(ctx, vols[i], dtype, geo[i], scr, ls[k]);
+            ctx->d_err = ctx_err;
+            if (st) return fail(st);
+        }
         if ((st = hip_check(hipEventRecord(ev[k], ls[k]), "join record"))) return fail(st);
         if ((st = hip_check(hipStreamWaitEvent(origin, ev[k], 0), "join wait"))) return fail(st);
     }
@@ -182,6 +193,30 @@ lt_status lt_batch_run(lt_batch* b, void* stream) {
     return hip_check(hipGraphLaunch(b->exec, (hipStream_t)stream), "hipGraphLaunch");
 }
 
+lt_status lt_batch_status(lt_batch* b, void* stream, int32_t* status) {
+    if (!b) return set_error(LT_E_ARG, "batch is NULL");
+    lt_status st = hip_check(hipSetDevice(b->ctx->device), "hipSetDevice");
+    if (st) return st;
+    if ((st = hip_check(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize"))) return st;
+    std::vector<uint32_t> w((size_t)std::max(b->n, 1), 0u);
+    if ((st = hip_check(hipMemcpy(w.data(), b->d_status, w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost),
+                        "read batch status")) ||
+        (st = hip_check(hipMemset(b->d_status, 0, w.size() * sizeof(uint32_t)), "clear batch status")))
+        return st;
+    lt_status first = LT_OK;
+    int bad = -1;
+    for (int i = 0; i < b->n; ++i) {
+        const lt_status v = (w[i] & ERR_LABEL) ? LT_E_LABEL_RANGE : (w[i] & ERR_OVERFLOW) ? LT_E_OVERFLOW : LT_OK;
+        if (status) status[i] = (int32_t)v;
+        if (v != LT_OK && first == LT_OK) {
+            first = v;
+            bad = i;
+        }
+    }
+    if (first != LT_OK) return set_error(first, "volume %d of the batch: %s", bad, lt_status_str(first));
+    return LT_OK;
+}
+
 lt_status lt_batch_destroy(lt_batch* b) {
     if (!b) return LT_OK;
     (void)hipSetDevice(b->ctx->device);
@@ -189,6 +224,7 @@ lt_status lt_batch_destroy(lt_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->scratch) (void)hipFree(b->scratch);
+    if (b->d_status) (void)hipFree(b->d_status);
     delete b;
     return LT_OK;
 }

@@ -122,6 +122,8 @@ namespace lt {
 lt_status set_error(lt_status s, const char* fmt, ...);
 lt_status hip_check(hipError_t e, const char* what);
 lt_status ensure_scratch(lt_ctx* ctx, size_t bytes);
+// hipMalloc through the allocation fault injection (LT_FAULT_INJECT=alloc[:N]).
+lt_status device_alloc(void** p, size_t bytes, const char* what);
 lt_status geom_from(int ndim, const int64_t* shape, Geom* g);
 
 // Where the EDT x pass records bounding boxes (fused pipeline): device boxes of

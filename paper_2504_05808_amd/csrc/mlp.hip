@@ -266,7 +266,7 @@ static lt_status ensure_cap(lt_mlp* p, int B) {
     if (B <= p->cap) return LT_OK;
     if (p->act) (void)hipFree(p->act), p->act = nullptr;
     const int cap = (B + 255) & ~255;
-    lt_status st = hip_check(hipMalloc((void**)&p->act, act_bytes(cap)), "hipMalloc(mlp activations)");
+    lt_status st = device_alloc((void**)&p->act, act_bytes(cap), "hipMalloc(mlp activations)");
     if (!st) p->cap = cap;
     return st;
 }
@@ -316,9 +316,9 @@ lt_status lt_mlp_create(lt_ctx* ctx, uint64_t seed, lt_mlp** out) {
         p->fmax[k] = 1e30f;
     }
     const size_t pb = N_PARAM * sizeof(float);
-    if ((st = hip_check(hipMalloc((void**)&p->w, 4 * pb), "hipMalloc(mlp params)")) ||
-        (st = hip_check(hipMalloc((void**)&p->wb, N_PARAM * sizeof(uint16_t)), "hipMalloc(mlp bf16)")) ||
-        (st = hip_check(hipMalloc((void**)&p->consts, 4 * MLP_IN * sizeof(float)), "hipMalloc(mlp consts)"))) {
+    if ((st = device_alloc((void**)&p->w, 4 * pb, "hipMalloc(mlp params)")) ||
+        (st = device_alloc((void**)&p->wb, N_PARAM * sizeof(uint16_t), "hipMalloc(mlp bf16)")) ||
+        (st = device_alloc((void**)&p->consts, 4 * MLP_IN * sizeof(float), "hipMalloc(mlp consts)"))) {
         lt_mlp_destroy(p);
         return st;
     }

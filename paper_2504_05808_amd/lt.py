@@ -85,6 +85,7 @@ def load():
     lib.lt_batch_create.argtypes = [P, ctypes.POINTER(_Volume), I, I, ctypes.POINTER(P)]
     lib.lt_batch_run.argtypes = [P, V]
     lib.lt_batch_destroy.argtypes = [P]
+    lib.lt_batch_status.argtypes = [P, V, ctypes.POINTER(ctypes.c_int32)]
     lib.lt_get_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
     lib.lt_set_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
     lib.lt_autotune.argtypes = [P, P, I, I, i64p, U32, ctypes.c_char_p, I, ctypes.POINTER(_Tuning)]
@@ -100,7 +101,7 @@ def load():
               "lt_pipeline_static", "lt_mesh_measures", "lt_edt_aniso", "lt_thickness_aniso",
               "lt_object_measures_aniso", "lt_pipeline_aniso", "lt_filtered_roundness", "lt_remap_roundness",
               "lt_closed_forms", "lt_sync_status", "lt_profile_enable", "lt_profile_read",
-              "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run",
+              "lt_profile_reset", "lt_ctx_info", "lt_batch_create", "lt_batch_run", "lt_batch_status",
               "lt_batch_destroy", "lt_get_tuning", "lt_set_tuning", "lt_autotune",
               "lt_autotune_batch"):
         getattr(lib, f).restype = I
@@ -477,6 +478,13 @@ class Batch:
 
     def run(self, stream=None):
         _check(self._lib.lt_batch_run(self._h, _stream(stream)))
+
+    def status(self, stream=None) -> list[int]:
+        """Per-volume statuses of the replays so far (0 = ok, 6 = label out of range,
+        7 = overflow), read and cleared; see lt_batch_status."""
+        arr = (ctypes.c_int32 * len(self.outputs))()
+        self._lib.lt_batch_status(self._h, _stream(stream), arr)
+        return list(arr)
 
     def close(self):
         if getattr(self, "_h", None):

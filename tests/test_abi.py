@@ -152,3 +152,20 @@ def test_filtered_roundness_and_remap_argument_errors():
     assert r(ctx, p, 0, float("nan"), p, None) == 0              # nothing to do
     assert r(ctx, None, 4, float("nan"), p, None) == 1
     assert r(ctx, p, 4, float("inf"), p, None) == 1
+
+
+def test_injected_allocation_failure_on_context_create(monkeypatch):
+    """LT_FAULT_INJECT=alloc: a context needs device memory, so lt_ctx_create fails
+    with LT_E_ALLOC before touching the device, and leaves *out NULL; without the
+    variable the call goes on (LT_OK on a GPU machine, a HIP error without one)."""
+    lib = lt.load()
+    h = ctypes.c_void_p(123)
+    monkeypatch.setenv("LT_FAULT_INJECT", "alloc")
+    assert lib.lt_ctx_create(ctypes.byref(h), 0) == 4
+    assert h.value is None
+    assert b"injected" in lib.lt_last_error()
+    monkeypatch.delenv("LT_FAULT_INJECT")
+    st = lib.lt_ctx_create(ctypes.byref(h), 0)
+    assert st in (0, 5)
+    if st == 0:
+        lib.lt_ctx_destroy(h)
