@@ -9,15 +9,17 @@
 // training range, a non-finite output, or a correction larger than any seen in
 // training).
 //
-// Every matrix product goes through mfma_gemm (one wave per 16x16 output tile,
-// v_mfma_f32_16x16x16_bf16, K stepped by 16).  Weight gradients are full reductions
-// over the batch inside one GEMM and bias gradients are fixed-order column sums, so
-// a training step is deterministic.  Master weights and AdamW moments are FP32; the
-// BF16 copies used by the products are refreshed after every update.
+// A training step is two launches: a fused forward + backward per chunk of rows
+// (weights and activations in LDS, v_mfma_f32_16x16x16_bf16 tiles) writing partial
+// gradients, and a fixed-order reduction of the partials fused with AdamW; so a
+// step is deterministic.  Inference is one fused launch.  Master weights and AdamW
+// moments are FP32; the BF16 copies used by the products are refreshed after every
+// update.  mfma_gemm (one wave per 16x16 output tile) serves lt_bf16_gemm.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -78,95 +80,9 @@ mfma_gemm(int M, int N, int K, const uint16_t* __restrict__ A, int lda, int ta,
     for (int r = 0; r < 4; ++r) C[(size_t)(m0 + kq + r) * ldc + n0 + r16] = acc[r];
 }
 
-// x (B x 34 FP32 features) -> standardised BF16 rows of 48 (zero pad); rows
-// B .. Bp-1 (padding up to a multiple of 16) are zero.
-__global__ void mlp_prep_input(const float* __restrict__ x, int B, int Bp, const float* __restrict__ mean,
-                               const float* __restrict__ inv_std, uint16_t* __restrict__ xb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Bp * MLP_INP) return;
-    const int r = i / MLP_INP, c = i % MLP_INP;
-    float v = 0.f;
-    if (c < MLP_IN && r < B) {
-        v = (x[(size_t)r * MLP_IN + c] - mean[c]) * inv_std[c];
-        if (!isfinite(v)) v = 0.f;
-    }
-    xb[i] = f2bf(v);
-}
-
-// z += bias (in place, kept for the backward pass); h = bf16(silu(z)).
-__global__ void mlp_bias_silu(float* __restrict__ z, const float* __restrict__ bias, int B,
-                              uint16_t* __restrict__ h) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B * MLP_H) return;
-    const float v = z[i] + bias[i % MLP_H];
-    z[i] = v;
-    h[i] = f2bf(v / (1.f + expf(-v)));
-}
-
-// prediction p = o[:, 0] + b4; d o = 2 (p - y) / B in column 0 (BF16), loss terms.
-__global__ void mlp_loss_grad(const float* __restrict__ o, const float* __restrict__ b4,
-                              const float* __restrict__ y, int B, uint16_t* __restrict__ dob,
-                              float* __restrict__ dcol0, float* __restrict__ sq) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= B) return;
-    const float p = o[(size_t)r * MLP_OUTP] + b4[0];
-    const float d = 2.f * (p - y[r]) / (float)B;
-    for (int c = 0; c < MLP_OUTP; ++c) dob[(size_t)r * MLP_OUTP + c] = c == 0 ? f2bf(d) : (uint16_t)0;
-    dcol0[r] = d;
-    sq[r] = (p - y[r]) * (p - y[r]);
-}
-
-// dz = dh * silu'(z) -> BF16.
-__global__ void mlp_silu_back(const float* __restrict__ dh, const float* __restrict__ z, int B,
-                              uint16_t* __restrict__ dzb, float* __restrict__ dz) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B * MLP_H) return;
-    const float v = z[i];
-    const float s = 1.f / (1.f + expf(-v));
-    const float g = dh[i] * s * (1.f + v * (1.f - s));
-    dz[i] = g;
-    dzb[i] = f2bf(g);
-}
-
-// out[c] = sum over rows r of m[r * ld + c] in row order (one thread per column).
-__global__ void mlp_colsum(const float* __restrict__ m, int rows, int cols, int ld, float* __restrict__ out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += m[(size_t)r * ld + c];
-    out[c] = s;
-}
-
-// AdamW on the FP32 master weights (bias-corrected moments, decoupled weight
-// decay on matrices only), then refresh the BF16 copy.
-__global__ void mlp_adamw(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                          float* __restrict__ v, uint16_t* __restrict__ wb, int n, float lr, float wd,
-                          float b1, float b2, float eps, float c1, float c2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const bool is_bias = (i >= OFF_B1 && i < OFF_W2) || (i >= OFF_B2 && i < OFF_W3) ||
-                         (i >= OFF_B3 && i < OFF_W4) || i >= OFF_B4;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    float wi = w[i];
-    if (!is_bias) wi -= lr * wd * wi;
-    wi -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    w[i] = wi;
-    wb[i] = f2bf(wi);
-}
-
 __global__ void mlp_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ wb, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) wb[i] = f2bf(w[i]);
-}
-
-__global__ void mlp_output(const float* __restrict__ o, const float* __restrict__ b4, int B, float scale,
-                           float shift, float* __restrict__ out) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < B) out[r] = (o[(size_t)r * MLP_OUTP] + b4[0]) * scale + shift;
 }
 
 // Features of lt_object_measures outputs: hist (32), log V, mean LT / V^(1/3).
@@ -195,6 +111,287 @@ __global__ void mlp_guard(const float* __restrict__ x, const float* __restrict__
     if (!ok) atomicAdd(n_fallback, 1u);
 }
 
+// ------------------------------------------------------------------ fused step
+//
+// A training step runs as two kernels.  mlp_fused_fwd_bwd: one workgroup per chunk
+// of FB_ROWS rows keeps the BF16 weights, its activations and their gradients in
+// LDS; forward (standardisation, three bias + SiLU layers, output), loss gradient
+// and backward through every layer run back to back, and the chunk writes its
+// partial weight and bias gradients (and its sum of squared errors).  Rows past the
+// batch get a zero loss gradient, so they add nothing.  mlp_reduce_adamw sums the
+// chunks' partials in chunk order (deterministic) into the gradient, then applies
+// AdamW and refreshes the BF16 copy.  The BF16 rounding points are those of the
+// unfused layers: inputs, hidden activations, output gradient and hidden
+// pre-activation gradients enter the products as BF16; bias gradients sum the FP32
+// pre-activation gradients.
+constexpr int FB_ROWS = 32;                            // rows per workgroup
+constexpr int FB_THREADS = 256;
+
+// One 16 x 16 tile of C = A B from LDS operands with element strides:
+// A(i, k) = A[i * ai + k * ak], B(k, j) = B[k * bk + j * bj].  Lane l supplies
+// A(m0 + l % 16, k0 + 4 (l / 16) + q) and B(k0 + 4 (l / 16) + q, n0 + l % 16) and
+// holds C(m0 + 4 (l / 16) + r, n0 + l % 16) in acc[r].
+__device__ __forceinline__ f32x4 lds_tile(const uint16_t* A, int ai, int ak, const uint16_t* B, int bk, int bj,
+                                          int m0, int n0, int K, int lane) {
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + kq + q;
+            a[q] = (short)A[(m0 + r16) * ai + k * ak];
+            b[q] = (short)B[k * bk + (n0 + r16) * bj];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+struct FusedLds {
+    uint16_t *w1, *w2, *w3, *w4;       // BF16 weights [64][48], [64][64], [64][64], [16][64]
+    float* b;                          // b1 b2 b3 [64 each], b4 [16]
+    uint16_t* xb;                      // [R][48]
+    uint16_t *h1, *h2, *h3;            // [R][64]
+    float *z1, *z2, *z3;               // [R][64] pre-activations
+    float* o;                          // [R][16]
+    uint16_t* dob;                     // [R][16]
+    float* d;                          // [R][64] FP32 gradient of the current layer
+    uint16_t* db;                      // [R][64] its BF16 copy
+};
+
+__host__ __device__ constexpr size_t fused_lds_bytes(bool train) {
+    return (size_t)(MLP_H * MLP_INP + 2 * MLP_H * MLP_H + MLP_OUTP * MLP_H) * 2 + (3 * MLP_H + MLP_OUTP) * 4 +
+           (size_t)FB_ROWS * MLP_INP * 2 + 3 * (size_t)FB_ROWS * MLP_H * 2 +
+           (train ? 3 * (size_t)FB_ROWS * MLP_H * 4 : 0) + (size_t)FB_ROWS * MLP_OUTP * 4 +
+           (train ? (size_t)FB_ROWS * MLP_OUTP * 2 + (size_t)FB_ROWS * MLP_H * 6 : 0) + 64;
+}
+
+__device__ FusedLds fused_layout(char* base, bool train) {
+    FusedLds L;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base + at;
+        at += (bytes + 7) & ~size_t(7);
+        return p;
+    };
+    L.w1 = (uint16_t*)take(MLP_H * MLP_INP * 2);
+    L.w2 = (uint16_t*)take(MLP_H * MLP_H * 2);
+    L.w3 = (uint16_t*)take(MLP_H * MLP_H * 2);
+    L.w4 = (uint16_t*)take(MLP_OUTP * MLP_H * 2);
+    L.b = (float*)take((3 * MLP_H + MLP_OUTP) * 4);
+    L.xb = (uint16_t*)take(FB_ROWS * MLP_INP * 2);
+    L.h1 = (uint16_t*)take(FB_ROWS * MLP_H * 2);
+    L.h2 = (uint16_t*)take(FB_ROWS * MLP_H * 2);
+    L.h3 = (uint16_t*)take(FB_ROWS * MLP_H * 2);
+    L.z1 = train ? (float*)take(FB_ROWS * MLP_H * 4) : nullptr;
+    L.z2 = train ? (float*)take(FB_ROWS * MLP_H * 4) : nullptr;
+    L.z3 = train ? (float*)take(FB_ROWS * MLP_H * 4) : nullptr;
+    L.o = (float*)take(FB_ROWS * MLP_OUTP * 4);
+    L.dob = train ? (uint16_t*)take(FB_ROWS * MLP_OUTP * 2) : nullptr;
+    L.d = train ? (float*)take(FB_ROWS * MLP_H * 4) : nullptr;
+    L.db = train ? (uint16_t*)take(FB_ROWS * MLP_H * 2) : nullptr;
+    return L;
+}
+
+// Weights, biases and the chunk's standardised BF16 inputs into LDS.
+__device__ void fused_load(const FusedLds& L, const uint16_t* __restrict__ wb, const float* __restrict__ w,
+                           const float* __restrict__ x, int B, int r0, const float* __restrict__ mean,
+                           const float* __restrict__ inv_std, int tid) {
+    for (int i = tid; i < MLP_H * MLP_INP; i += FB_THREADS) L.w1[i] = wb[OFF_W1 + i];
+    for (int i = tid; i < MLP_H * MLP_H; i += FB_THREADS) {
+        L.w2[i] = wb[OFF_W2 + i];
+        L.w3[i] = wb[OFF_W3 + i];
+    }
+    for (int i = tid; i < MLP_OUTP * MLP_H; i += FB_THREADS) L.w4[i] = wb[OFF_W4 + i];
+    for (int i = tid; i < MLP_H; i += FB_THREADS) {
+        L.b[i] = w[OFF_B1 + i];
+        L.b[MLP_H + i] = w[OFF_B2 + i];
+        L.b[2 * MLP_H + i] = w[OFF_B3 + i];
+    }
+    if (tid < MLP_OUTP) L.b[3 * MLP_H + tid] = w[OFF_B4 + tid];
+    for (int i = tid; i < FB_ROWS * MLP_INP; i += FB_THREADS) {
+        const int r = i / MLP_INP, c = i % MLP_INP;
+        float v = 0.f;
+        if (c < MLP_IN && r0 + r < B) {
+            v = (x[(size_t)(r0 + r) * MLP_IN + c] - mean[c]) * inv_std[c];
+            if (!isfinite(v)) v = 0.f;
+        }
+        L.xb[i] = f2bf(v);
+    }
+}
+
+// Forward of the chunk: z = h_prev W^T + b (kept with TRAIN), h = bf16(silu(z)); o =
+// h3 W4^T (without b4).  Each wave takes tiles round-robin.
+template <bool TRAIN>
+__device__ void fused_forward(const FusedLds& L, int wid, int lane) {
+    const uint16_t* hin[3] = {L.xb, L.h1, L.h2};
+    uint16_t* hout[3] = {L.h1, L.h2, L.h3};
+    float* zout[3] = {L.z1, L.z2, L.z3};
+    const uint16_t* wt[3] = {L.w1, L.w2, L.w3};
+    const int kin[3] = {MLP_INP, MLP_H, MLP_H};
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    for (int layer = 0; layer < 3; ++layer) {
+        const int K = kin[layer];
+        for (int t = wid; t < (FB_ROWS / 16) * (MLP_H / 16); t += FB_THREADS / 64) {
+            const int m0 = (t / (MLP_H / 16)) * 16, n0 = (t % (MLP_H / 16)) * 16;
+            const f32x4 acc = lds_tile(hin[layer], K, 1, wt[layer], 1, K, m0, n0, K, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + kq + r, col = n0 + r16;
+                const float v = acc[r] + L.b[layer * MLP_H + col];
+                if (TRAIN) zout[layer][row * MLP_H + col] = v;
+                hout[layer][row * MLP_H + col] = f2bf(v / (1.f + expf(-v)));
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = wid; t < FB_ROWS / 16; t += FB_THREADS / 64) {
+        const int m0 = t * 16;
+        const f32x4 acc = lds_tile(L.h3, MLP_H, 1, L.w4, 1, MLP_H, m0, 0, MLP_H, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) L.o[(m0 + kq + r) * MLP_OUTP + r16] = acc[r];
+    }
+    __syncthreads();
+}
+
+// Training: forward, loss gradient and backward of one chunk; partial gradients to
+// part[chunk][N_PARAM] and the chunk's sum of squared errors to sse[chunk].
+__global__ void __launch_bounds__(FB_THREADS)
+mlp_fused_fwd_bwd(const float* __restrict__ x, const float* __restrict__ y, int B,
+                  const float* __restrict__ consts, const float* __restrict__ w, const uint16_t* __restrict__ wb,
+                  float* __restrict__ part, float* __restrict__ sse) {
+    extern __shared__ __align__(16) char lds[];
+    const FusedLds L = fused_layout(lds, true);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int chunk = blockIdx.x, r0 = chunk * FB_ROWS;
+    fused_load(L, wb, w, x, B, r0, consts, consts + MLP_IN, tid);
+    __syncthreads();
+    fused_forward<true>(L, wid, lane);
+    float* P = part + (size_t)chunk * N_PARAM;
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    // loss gradient: d = 2 (p - y) / B in output column 0 (rows past B: 0)
+    if (tid < FB_ROWS) {
+        const int r = tid;
+        float d = 0.f;
+        if (r0 + r < B) d = 2.f * (L.o[r * MLP_OUTP] + L.b[3 * MLP_H] - y[r0 + r]) / (float)B;
+        for (int c = 0; c < MLP_OUTP; ++c) L.dob[r * MLP_OUTP + c] = c == 0 ? f2bf(d) : (uint16_t)0;
+        L.d[r] = d;                                        // column 0 of d, for db4
+    }
+    __syncthreads();
+    if (tid == 0) {                                        // db4 and the squared errors, in row order
+        float db4 = 0.f, sq = 0.f;
+        for (int r = 0; r < FB_ROWS && r0 + r < B; ++r) {
+            db4 += L.d[r];
+            const float e = L.o[r * MLP_OUTP] + L.b[3 * MLP_H] - y[r0 + r];
+            sq += e * e;
+        }
+        P[OFF_B4] = db4;
+        sse[chunk] = sq;
+    }
+    if (tid > 0 && tid < MLP_OUTP) P[OFF_B4 + tid] = 0.f;
+    // dW4 [16][64] = dob^T h3; dh3 [R][64] = dob W4
+    for (int t = wid; t < MLP_H / 16; t += FB_THREADS / 64) {
+        const f32x4 acc = lds_tile(L.dob, 1, MLP_OUTP, L.h3, MLP_H, 1, 0, t * 16, FB_ROWS, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[OFF_W4 + (kq + r) * MLP_H + t * 16 + r16] = acc[r];
+    }
+    __syncthreads();                                       // L.d (column 0) is read above
+    for (int t = wid; t < (FB_ROWS / 16) * (MLP_H / 16); t += FB_THREADS / 64) {
+        const int m0 = (t / (MLP_H / 16)) * 16, n0 = (t % (MLP_H / 16)) * 16;
+        const f32x4 acc = lds_tile(L.dob, MLP_OUTP, 1, L.w4, MLP_H, 1, m0, n0, MLP_OUTP, lane);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) L.d[(m0 + kq + r) * MLP_H + n0 + r16] = acc[r];
+    }
+    __syncthreads();
+    const float* zs[3] = {L.z1, L.z2, L.z3};
+    const uint16_t* hprev[3] = {L.xb, L.h1, L.h2};
+    const uint16_t* wt[3] = {L.w1, L.w2, L.w3};
+    const int kin[3] = {MLP_INP, MLP_H, MLP_H};
+    const int offw[3] = {OFF_W1, OFF_W2, OFF_W3}, offb[3] = {OFF_B1, OFF_B2, OFF_B3};
+    for (int layer = 2; layer >= 0; --layer) {
+        // dz = dh * silu'(z) (FP32 and BF16)
+        for (int i = tid; i < FB_ROWS * MLP_H; i += FB_THREADS) {
+            const float v = zs[layer][i];
+            const float sg = 1.f / (1.f + expf(-v));
+            const float g = L.d[i] * sg * (1.f + v * (1.f - sg));
+            L.d[i] = g;
+            L.db[i] = f2bf(g);
+        }
+        __syncthreads();
+        // db = column sums of dz in row order
+        if (tid < MLP_H) {
+            float sb = 0.f;
+            for (int r = 0; r < FB_ROWS; ++r) sb += L.d[r * MLP_H + tid];
+            P[offb[layer] + tid] = sb;
+        }
+        // dW [64][K] = dz^T h_prev
+        const int K = kin[layer];
+        for (int t = wid; t < (MLP_H / 16) * (K / 16); t += FB_THREADS / 64) {
+            const int m0 = (t / (K / 16)) * 16, n0 = (t % (K / 16)) * 16;
+            const f32x4 acc = lds_tile(L.db, 1, MLP_H, hprev[layer], K, 1, m0, n0, FB_ROWS, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[offw[layer] + (m0 + kq + r) * K + n0 + r16] = acc[r];
+        }
+        if (layer == 0) break;
+        __syncthreads();                                   // every lane has read L.d for db
+        // dh_prev [R][64] = dz W (layer's weights [64][K], K = 64 here)
+        for (int t = wid; t < (FB_ROWS / 16) * (MLP_H / 16); t += FB_THREADS / 64) {
+            const int m0 = (t / (MLP_H / 16)) * 16, n0 = (t % (MLP_H / 16)) * 16;
+            const f32x4 acc = lds_tile(L.db, MLP_H, 1, wt[layer], K, 1, m0, n0, MLP_H, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) L.d[(m0 + kq + r) * MLP_H + n0 + r16] = acc[r];
+        }
+        __syncthreads();
+    }
+}
+
+// Gradient = chunk partials summed in chunk order; with lr > 0 AdamW on the FP32
+// master weights (bias-corrected moments, decoupled weight decay on matrices) and
+// the BF16 refresh.  Thread 0 also sums the chunks' squared errors into sse_out.
+__global__ void mlp_reduce_adamw(const float* __restrict__ part, int nchunk, const float* __restrict__ sse,
+                                 float* __restrict__ sse_out, float* __restrict__ w, float* __restrict__ g,
+                                 float* __restrict__ m, float* __restrict__ v, uint16_t* __restrict__ wb, float lr,
+                                 float wd, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && sse_out) {
+        float sq = 0.f;
+        for (int c = 0; c < nchunk; ++c) sq += sse[c];
+        *sse_out = sq;
+    }
+    if (i >= N_PARAM) return;
+    float gi = 0.f;
+    for (int c = 0; c < nchunk; ++c) gi += part[(size_t)c * N_PARAM + i];
+    g[i] = gi;
+    if (!(lr > 0.f)) return;
+    const bool is_bias = (i >= OFF_B1 && i < OFF_W2) || (i >= OFF_B2 && i < OFF_W3) ||
+                         (i >= OFF_B3 && i < OFF_W4) || i >= OFF_B4;
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float wi = w[i];
+    if (!is_bias) wi -= lr * wd * wi;
+    wi -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+}
+
+// Inference: forward of a chunk and the de-standardised output (b4 added).
+__global__ void __launch_bounds__(FB_THREADS)
+mlp_fused_infer(const float* __restrict__ x, int B, const float* __restrict__ consts,
+                const float* __restrict__ w, const uint16_t* __restrict__ wb, float scale, float shift,
+                float* __restrict__ out) {
+    extern __shared__ __align__(16) char lds[];
+    const FusedLds L = fused_layout(lds, false);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r0 = blockIdx.x * FB_ROWS;
+    fused_load(L, wb, w, x, B, r0, consts, consts + MLP_IN, tid);
+    __syncthreads();
+    fused_forward<false>(L, wid, lane);
+    if (tid < FB_ROWS && r0 + tid < B) out[r0 + tid] = (L.o[tid * MLP_OUTP] + L.b[3 * MLP_H]) * scale + shift;
+}
+
 }  // namespace lt
 
 struct lt_mlp {
@@ -208,50 +405,10 @@ struct lt_mlp {
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     uint16_t* wb = nullptr;
     float* consts = nullptr;     // mean[34], inv_std[34], fmin[34], fmax[34]
-    char* act = nullptr;         // activations for `cap` rows
+    float* part = nullptr;       // per-chunk gradient partials and squared errors for `cap` rows
 };
 
 namespace lt {
-
-struct Act {
-    uint16_t *xb, *h1, *h2, *h3, *dob, *dz3b, *dz2b, *dz1b;
-    float *z1, *z2, *z3, *o, *dh, *dz, *dcol0, *sq, *pred;
-};
-
-static size_t act_bytes(int cap) {
-    const size_t c = (size_t)cap;
-    return c * (MLP_INP + 3 * MLP_H + MLP_OUTP + 3 * MLP_H) * 2 +
-           c * (3 * MLP_H + MLP_OUTP + 2 * MLP_H + 3) * 4 + 32 * 256;   // + per-array alignment slack
-}
-
-static Act act_layout(char* base, int cap) {
-    Act a;
-    size_t at = 0;
-    auto take = [&](size_t bytes) {
-        char* p = base + at;
-        at += (bytes + 255) & ~size_t(255);
-        return p;
-    };
-    const size_t c = (size_t)cap;
-    a.xb = (uint16_t*)take(c * MLP_INP * 2);
-    a.h1 = (uint16_t*)take(c * MLP_H * 2);
-    a.h2 = (uint16_t*)take(c * MLP_H * 2);
-    a.h3 = (uint16_t*)take(c * MLP_H * 2);
-    a.dob = (uint16_t*)take(c * MLP_OUTP * 2);
-    a.dz3b = (uint16_t*)take(c * MLP_H * 2);
-    a.dz2b = (uint16_t*)take(c * MLP_H * 2);
-    a.dz1b = (uint16_t*)take(c * MLP_H * 2);
-    a.z1 = (float*)take(c * MLP_H * 4);
-    a.z2 = (float*)take(c * MLP_H * 4);
-    a.z3 = (float*)take(c * MLP_H * 4);
-    a.o = (float*)take(c * MLP_OUTP * 4);
-    a.dh = (float*)take(c * MLP_H * 4);
-    a.dz = (float*)take(c * MLP_H * 4);
-    a.dcol0 = (float*)take(c * 4);
-    a.sq = (float*)take(c * 4);
-    a.pred = (float*)take(c * 4);
-    return a;
-}
 
 static inline unsigned nb(size_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -262,13 +419,29 @@ static void gemm(int M, int N, int K, const uint16_t* A, int lda, int ta, const 
     mfma_gemm<<<(tiles + 3) / 4, 256, 0, s>>>(M, N, K, A, lda, ta, B, ldb, tb, C, ldc);
 }
 
+static size_t part_floats(int cap) {
+    const size_t nchunk = (size_t)(cap + FB_ROWS - 1) / FB_ROWS;
+    return nchunk * N_PARAM + nchunk;
+}
+
 static lt_status ensure_cap(lt_mlp* p, int B) {
     if (B <= p->cap) return LT_OK;
-    if (p->act) (void)hipFree(p->act), p->act = nullptr;
+    if (p->part) (void)hipFree(p->part), p->part = nullptr;
     const int cap = (B + 255) & ~255;
-    lt_status st = device_alloc((void**)&p->act, act_bytes(cap), "hipMalloc(mlp activations)");
+    lt_status st = device_alloc((void**)&p->part, part_floats(cap) * sizeof(float), "hipMalloc(mlp partials)");
     if (!st) p->cap = cap;
     return st;
+}
+
+// Dynamic LDS limits of the fused kernels (above the 64 KiB default), set once.
+static void fused_attributes() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void*)mlp_fused_fwd_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)fused_lds_bytes(true));
+        (void)hipFuncSetAttribute((const void*)mlp_fused_infer, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)fused_lds_bytes(false));
+    });
 }
 
 static lt_status upload_consts(lt_mlp* p) {
@@ -278,21 +451,6 @@ static lt_status upload_consts(lt_mlp* p) {
     memcpy(h + 2 * MLP_IN, p->fmin, sizeof(p->fmin));
     memcpy(h + 3 * MLP_IN, p->fmax, sizeof(p->fmax));
     return hip_check(hipMemcpy(p->consts, h, sizeof(h), hipMemcpyHostToDevice), "copy mlp constants");
-}
-
-// Forward pass of the B rows of x (B x 34 FP32), computed on Bp >= B rows (a
-// multiple of 16 within capacity; the extra rows are zero inputs).
-static void forward(lt_mlp* p, const float* x, int Bvalid, int B, const Act& a, hipStream_t s) {
-    const float* mean = p->consts;
-    const float* inv_std = p->consts + MLP_IN;
-    mlp_prep_input<<<nb((size_t)B * MLP_INP), 256, 0, s>>>(x, Bvalid, B, mean, inv_std, a.xb);
-    gemm(B, MLP_H, MLP_INP, a.xb, MLP_INP, 0, p->wb + OFF_W1, MLP_INP, 1, a.z1, MLP_H, s, p->ctx);
-    mlp_bias_silu<<<nb((size_t)B * MLP_H), 256, 0, s>>>(a.z1, p->w + OFF_B1, B, a.h1);
-    gemm(B, MLP_H, MLP_H, a.h1, MLP_H, 0, p->wb + OFF_W2, MLP_H, 1, a.z2, MLP_H, s, p->ctx);
-    mlp_bias_silu<<<nb((size_t)B * MLP_H), 256, 0, s>>>(a.z2, p->w + OFF_B2, B, a.h2);
-    gemm(B, MLP_H, MLP_H, a.h2, MLP_H, 0, p->wb + OFF_W3, MLP_H, 1, a.z3, MLP_H, s, p->ctx);
-    mlp_bias_silu<<<nb((size_t)B * MLP_H), 256, 0, s>>>(a.z3, p->w + OFF_B3, B, a.h3);
-    gemm(B, MLP_OUTP, MLP_H, a.h3, MLP_H, 0, p->wb + OFF_W4, MLP_H, 1, a.o, MLP_OUTP, s, p->ctx);
 }
 
 }  // namespace lt
@@ -360,7 +518,7 @@ lt_status lt_mlp_destroy(lt_mlp* p) {
     if (p->w) (void)hipFree(p->w);
     if (p->wb) (void)hipFree(p->wb);
     if (p->consts) (void)hipFree(p->consts);
-    if (p->act) (void)hipFree(p->act);
+    if (p->part) (void)hipFree(p->part);
     delete p;
     return LT_OK;
 }
@@ -392,33 +550,27 @@ lt_status lt_mlp_train_step(lt_mlp* p, const float* x, const float* y, int B, fl
     if (B <= 0 || B % 16) return set_error(LT_E_ARG, "batch size must be a positive multiple of 16");
     lt_status st = hip_check(hipSetDevice(p->ctx->device), "hipSetDevice");
     if (st || (st = ensure_cap(p, B))) return st;
+    fused_attributes();
     hipStream_t s = (hipStream_t)stream;
-    const Act a = act_layout(p->act, p->cap);
-    forward(p, x, B, B, a, s);
-    mlp_loss_grad<<<nb(B), 256, 0, s>>>(a.o, p->w + OFF_B4, y, B, a.dob, a.dcol0, a.sq);
-    float* g = p->g;
-    mlp_colsum<<<1, 64, 0, s>>>(a.dcol0, B, 1, 1, g + OFF_B4);                          // db4
-    gemm(MLP_OUTP, MLP_H, B, a.dob, MLP_OUTP, 1, a.h3, MLP_H, 0, g + OFF_W4, MLP_H, s, p->ctx);   // dW4
-    gemm(B, MLP_H, MLP_OUTP, a.dob, MLP_OUTP, 0, p->wb + OFF_W4, MLP_H, 0, a.dh, MLP_H, s, p->ctx);  // dH3
-    mlp_silu_back<<<nb((size_t)B * MLP_H), 256, 0, s>>>(a.dh, a.z3, B, a.dz3b, a.dz);
-    mlp_colsum<<<1, 64, 0, s>>>(a.dz, B, MLP_H, MLP_H, g + OFF_B3);
-    gemm(MLP_H, MLP_H, B, a.dz3b, MLP_H, 1, a.h2, MLP_H, 0, g + OFF_W3, MLP_H, s, p->ctx);        // dW3
-    gemm(B, MLP_H, MLP_H, a.dz3b, MLP_H, 0, p->wb + OFF_W3, MLP_H, 0, a.dh, MLP_H, s, p->ctx);   // dH2
-    mlp_silu_back<<<nb((size_t)B * MLP_H), 256, 0, s>>>(a.dh, a.z2, B, a.dz2b, a.dz);
-    mlp_colsum<<<1, 64, 0, s>>>(a.dz, B, MLP_H, MLP_H, g + OFF_B2);
-    gemm(MLP_H, MLP_H, B, a.dz2b, MLP_H, 1, a.h1, MLP_H, 0, g + OFF_W2, MLP_H, s, p->ctx);        // dW2
-    gemm(B, MLP_H, MLP_H, a.dz2b, MLP_H, 0, p->wb + OFF_W2, MLP_H, 0, a.dh, MLP_H, s, p->ctx);   // dH1
-    mlp_silu_back<<<nb((size_t)B * MLP_H), 256, 0, s>>>(a.dh, a.z1, B, a.dz1b, a.dz);
-    mlp_colsum<<<1, 64, 0, s>>>(a.dz, B, MLP_H, MLP_H, g + OFF_B1);
-    gemm(MLP_H, MLP_INP, B, a.dz1b, MLP_H, 1, a.xb, MLP_INP, 0, g + OFF_W1, MLP_INP, s, p->ctx);  // dW1
+    const int nchunk = (B + FB_ROWS - 1) / FB_ROWS;
+    float* sse = p->part + (size_t)nchunk * N_PARAM;
+    {
+        ProfScope _p(p->ctx, s, "mlp_fused_fwd_bwd");
+        mlp_fused_fwd_bwd<<<nchunk, FB_THREADS, fused_lds_bytes(true), s>>>(x, y, B, p->consts, p->w, p->wb, p->part,
+                                                                          sse);
+    }
+    float c1 = 1.f, c2 = 1.f;
+    const float b1 = 0.9f, b2 = 0.999f;
     if (lr > 0.f) {
         p->step += 1;
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float c1 = 1.f - powf(b1, (float)p->step), c2 = 1.f - powf(b2, (float)p->step);
-        mlp_adamw<<<nb(N_PARAM), 256, 0, s>>>(p->w, g, p->m, p->v, p->wb, N_PARAM, lr, weight_decay, b1,
-                                              b2, 1e-8f, c1, c2);
+        c1 = 1.f - powf(b1, (float)p->step);
+        c2 = 1.f - powf(b2, (float)p->step);
     }
-    if (loss_out) mlp_colsum<<<1, 64, 0, s>>>(a.sq, B, 1, 1, loss_out);                   // sum of squares
+    {
+        ProfScope _p(p->ctx, s, "mlp_reduce_adamw");
+        mlp_reduce_adamw<<<nb(N_PARAM), 256, 0, s>>>(p->part, nchunk, sse, loss_out, p->w, p->g, p->m, p->v, p->wb,
+                                                     lr, weight_decay, b1, b2, 1e-8f, c1, c2);
+    }
     return hip_check(hipGetLastError(), "mlp train step");
 }
 
@@ -426,12 +578,14 @@ lt_status lt_mlp_infer(lt_mlp* p, const float* x, int B, float* delta, void* str
     if (!p || (B > 0 && (!x || !delta))) return set_error(LT_E_ARG, "NULL argument");
     if (B <= 0) return LT_OK;
     lt_status st = hip_check(hipSetDevice(p->ctx->device), "hipSetDevice");
-    const int Bp = (B + 15) & ~15;
-    if (st || (st = ensure_cap(p, Bp))) return st;
+    if (st) return st;
+    fused_attributes();
     hipStream_t s = (hipStream_t)stream;
-    const Act a = act_layout(p->act, p->cap);
-    forward(p, x, B, Bp, a, s);
-    mlp_output<<<nb(B), 256, 0, s>>>(a.o, p->w + OFF_B4, B, p->t_scale, p->t_shift, delta);
+    {
+        ProfScope _p(p->ctx, s, "mlp_fused_infer");
+        mlp_fused_infer<<<(B + FB_ROWS - 1) / FB_ROWS, FB_THREADS, fused_lds_bytes(false), s>>>(
+            x, B, p->consts, p->w, p->wb, p->t_scale, p->t_shift, delta);
+    }
     return hip_check(hipGetLastError(), "mlp infer");
 }
 
