@@ -12,142 +12,181 @@
 // Each pass searches outward from p and stops as soon as k^2 reaches the best value
 // found, so the search is exact and costs O(sqrt(D)) loads per voxel.  Lanes of a
 // wave hold consecutive x, so every load of a pass is a coalesced row access.
+#include <type_traits>
+
 #include "lt_internal.h"
 
 namespace lt {
 
-// Pass x: one block per row.  A wave takes 64 consecutive voxels; ballots give the
-// positions where a run starts (label differs from the left neighbour, or x = 0)
-// and ends.  A voxel's run [s, e] is found from the nearest start at or before it
-// and the nearest end at or after it -- in its own chunk via bit scans, otherwise
-// from the per-chunk extremes kept in LDS -- and g = min(x - s + 1, e - x + 1).
-// With BOX, the first voxel of every object run also merges (z, y, run) into the
-// block's label table in LDS (bounding boxes of the fused pipeline); a block walks
-// consecutive slices of one row index y, so an object's runs meet in few blocks,
-// and the table is flushed to the global boxes once per block.
+// Pass x: each wave takes whole rows, one at a time, with no block barrier.  All
+// MAXC 64-voxel chunks of a row are loaded at once (their loads in flight
+// together); a voxel's left and right neighbours come from the adjacent lanes by
+// DPP lane shifts (across a chunk edge by readlane of the neighbouring chunk).
+// Ballots give, per chunk, the positions where a run starts (label differs from
+// the left neighbour, or x = 0) and ends; these masks are wave-uniform, so the
+// nearest start before a chunk and the nearest end after it are scalars carried
+// along the row.  A voxel's run [s, e] comes from its own chunk's masks by bit
+// scans, else from those scalars, and g = min(x - s + 1, e - x + 1).
+// With BOX, the object runs of a row are compacted into the wave's list in LDS
+// (label, start, end) and merged with the row's z into the block's label table,
+// 64 runs per pass (bounding boxes of the fused pipeline); all waves of a block walk
+// slices of one row index y, so the table holds z and x extents only (y is the
+// block's), an object's runs meet in few blocks, and the table is flushed to the
+// global boxes once per block.  The next row's labels are loaded while a row is
+// processed.
 constexpr int XBOX_TAB = 128;
-constexpr int XR = 8;                // slices per round of the x pass
+constexpr int XW = 16;                               // waves per block of the x pass
+constexpr int XRUNS = 64;                            // run list entries per wave
 
-template <typename L, bool BOX>
-__global__ void __launch_bounds__(1024)
+template <typename L, bool BOX, int MAXC>
+__global__ void __launch_bounds__(64 * XW)
 edt_pass_x(const L* __restrict__ lab, uint16_t* __restrict__ g, int nx, int ny, int nz, uint32_t* err,
            BoxTarget box, int zper) {
-    __shared__ unsigned long long s_start[XR][ROW_MAX_CHUNKS], s_end[XR][ROW_MAX_CHUNKS];
     __shared__ uint32_t s_key[BOX ? XBOX_TAB : 1];
-    __shared__ int s_bb[6][BOX ? XBOX_TAB : 1];
+    __shared__ int s_bb[4][BOX ? XBOX_TAB : 1];          // zmin, zmax, xmin, xmax
+    __shared__ uint32_t s_run[BOX ? XW : 1][BOX ? 3 * XRUNS : 1];
     const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    const int nw = blockDim.x >> 6;
-    const int chunks = (nx + 63) >> 6;
+    const int chunks = (nx + 63) >> 6;                 // <= MAXC
     const int y = blockIdx.y;
     if (BOX) {
         for (int t = threadIdx.x; t < XBOX_TAB; t += blockDim.x) {
             s_key[t] = 0u;
-            s_bb[0][t] = s_bb[2][t] = s_bb[4][t] = 0x7fffffff;
-            s_bb[1][t] = s_bb[3][t] = s_bb[5][t] = -1;
+            s_bb[0][t] = s_bb[2][t] = 0x7fffffff;
+            s_bb[1][t] = s_bb[3][t] = -1;
         }
         __syncthreads();
     }
     const int zb = blockIdx.z * zper, ze = min(nz, zb + zper);
-  // XR slices per round: their loads are in flight together and they share the
-  // round's two barriers
-  for (int z0 = zb; z0 < ze; z0 += XR) {
-    for (int c = wid; c < chunks; c += nw) {
-        const int x = c * 64 + lane;
-        L lv[XR], lm[XR], lp[XR];
-#pragma unroll
-        for (int q = 0; q < XR; ++q) {
-            const bool ok = z0 + q < ze && x < nx;
-            const L* r = lab + ((size_t)(z0 + q) * ny + y) * nx;
-            lv[q] = ok ? r[x] : L(0);
-            lm[q] = ok && x > 0 ? r[x - 1] : L(0);
-            lp[q] = ok && x + 1 < nx ? r[x + 1] : L(0);
-        }
-#pragma unroll
-        for (int q = 0; q < XR; ++q) {
-            const bool ok = z0 + q < ze && x < nx;
-            bool st = false, en = false;
-            if (ok) {
-                if (label_negative(lv[q])) atomicOr(err, ERR_LABEL);
-                st = x == 0 || lm[q] != lv[q];
-                en = x == nx - 1 || lp[q] != lv[q];
-            }
-            const unsigned long long ms = __ballot(st), me = __ballot(en);
-            if (lane == 0) {
-                s_start[q][c] = ms;
-                s_end[q][c] = me;
+    bool bad = false;
+    uint32_t* runs = s_run[BOX ? wid : 0];
+    // merge the wave's listed runs (n of them, row z) into the block table
+    auto merge_runs = [&](int n, int z) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < n) {
+            const uint32_t l = runs[3 * lane];
+            const int s0 = (int)runs[3 * lane + 1], e0 = (int)runs[3 * lane + 2];
+            const int slot = lds_slot<XBOX_TAB>(s_key, l);
+            if (slot >= 0) {
+                atomicMin(&s_bb[0][slot], z);
+                atomicMax(&s_bb[1][slot], z);
+                atomicMin(&s_bb[2][slot], s0);
+                atomicMax(&s_bb[3][slot], e0);
+            } else {
+                atomicMin(&box.bb[0 * box.nlab + l], z);
+                atomicMax(&box.bb[1 * box.nlab + l], z);
+                atomicMin(&box.bb[2 * box.nlab + l], y);
+                atomicMax(&box.bb[3 * box.nlab + l], y);
+                atomicMin(&box.bb[4 * box.nlab + l], s0);
+                atomicMax(&box.bb[5 * box.nlab + l], e0);
             }
         }
-    }
-    __syncthreads();
-    for (int c = wid; c < chunks; c += nw) {
-        const int x = c * 64 + lane;
-        if (x >= nx) continue;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    auto load_row = [&](int z, uint32_t (&v)[MAXC]) {
+        const L* r = lab + ((size_t)z * ny + y) * nx;
 #pragma unroll
-        for (int q = 0; q < XR; ++q) {
-            const int z = z0 + q;
-            if (z >= ze) break;
-            const size_t row = (size_t)z * ny + y;
-            const L l = lab[row * nx + x];
+        for (int c = 0; c < MAXC; ++c) {
+            const int x = c * 64 + lane;
+            v[c] = (z < ze && c < chunks && x < nx) ? (uint32_t)r[x] : 0u;
+        }
+    };
+    uint32_t nv[MAXC];
+    load_row(zb + wid, nv);
+    for (int z = zb + wid; z < ze; z += XW) {
+        const size_t row = (size_t)z * ny + y;
+        uint32_t v[MAXC];
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) v[c] = nv[c];
+        load_row(z + XW, nv);
+        // run starts and ends per chunk (wave-uniform masks)
+        unsigned long long st[MAXC], en[MAXC];
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            if (c >= chunks) {
+                st[c] = en[c] = 0ull;
+                continue;
+            }
+            const int x = c * 64 + lane;
+            // left neighbour: lane - 1, lane 0 takes lane 63 of the previous chunk
+            const uint32_t left_edge = c > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)v[c > 0 ? c - 1 : 0], 63) : 0u;
+            const uint32_t right_edge =
+                c + 1 < chunks ? (uint32_t)__builtin_amdgcn_readlane((int)v[c + 1 < MAXC ? c + 1 : c], 0) : 0u;
+            const uint32_t lm = (uint32_t)__builtin_amdgcn_update_dpp((int)left_edge, (int)v[c], 0x138, 0xf, 0xf, false);
+            const uint32_t lp = (uint32_t)__builtin_amdgcn_update_dpp((int)right_edge, (int)v[c], 0x130, 0xf, 0xf, false);
+            const bool in = x < nx;
+            st[c] = __ballot(in && (x == 0 || lm != v[c]));
+            en[c] = __ballot(in && (x == nx - 1 || lp != v[c]));
+        }
+        // nearest end after each chunk, from the right (scalars)
+        int next_end[MAXC];
+        {
+            int ne = nx - 1;
+#pragma unroll
+            for (int c = MAXC - 1; c >= 0; --c) {
+                next_end[c] = ne;
+                if (c < chunks && en[c]) ne = c * 64 + __ffsll(en[c]) - 1;
+            }
+        }
+        int prev_start = 0;                             // last start before the chunk
+        int nrun = 0;                                   // listed runs of this row (wave-uniform)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            if (c >= chunks) break;
+            const int x = c * 64 + lane;
+            const uint32_t l = v[c];
             int out = 0;
-            if (l != 0) {
-                const unsigned long long below = s_start[q][c] & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
-                int s0;
-                if (below) {
-                    s0 = c * 64 + 63 - __clzll(below);
-                } else {
-                    int cc = c - 1;
-                    while (s_start[q][cc] == 0ull) --cc;       // chunk 0 always has a start at x = 0
-                    s0 = cc * 64 + 63 - __clzll(s_start[q][cc]);
-                }
-                const unsigned long long above = s_end[q][c] & ~((1ull << lane) - 1ull);
-                int e0;
-                if (above) {
-                    e0 = c * 64 + __ffsll(above) - 1;
-                } else {
-                    int cc = c + 1;
-                    while (s_end[q][cc] == 0ull) ++cc;         // the last chunk ends at x = nx - 1
-                    e0 = cc * 64 + __ffsll(s_end[q][cc]) - 1;
-                }
+            bool first = false;
+            int s0 = 0, e0 = 0;
+            if (x < nx && l != 0u) {
+                bad |= label_negative(L(l));
+                const unsigned long long below = st[c] & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+                s0 = below ? c * 64 + 63 - __clzll(below) : prev_start;
+                const unsigned long long above = en[c] & ~((1ull << lane) - 1ull);
+                e0 = above ? c * 64 + __ffsll(above) - 1 : next_end[c];
                 out = min(x - s0 + 1, e0 - x + 1);
-                if (BOX && x == s0) {                          // first voxel of its run
-                    if ((uint64_t)l > box.max_label) {
-                        atomicOr(err, ERR_LABEL);
-                    } else if (!label_negative(l)) {
-                        const uint32_t u = (uint32_t)l;
-                        const int slot = lds_slot<XBOX_TAB>(s_key, u);
-                        if (slot >= 0) {
-                            atomicMin(&s_bb[0][slot], z);
-                            atomicMax(&s_bb[1][slot], z);
-                            atomicMin(&s_bb[2][slot], y);
-                            atomicMax(&s_bb[3][slot], y);
-                            atomicMin(&s_bb[4][slot], s0);
-                            atomicMax(&s_bb[5][slot], e0);
-                        } else {
-                            atomicMin(&box.bb[0 * box.nlab + u], z);
-                            atomicMax(&box.bb[1 * box.nlab + u], z);
-                            atomicMin(&box.bb[2 * box.nlab + u], y);
-                            atomicMax(&box.bb[3 * box.nlab + u], y);
-                            atomicMin(&box.bb[4 * box.nlab + u], s0);
-                            atomicMax(&box.bb[5 * box.nlab + u], e0);
-                        }
-                    }
+                if (BOX && x == s0) {                   // first voxel of its run
+                    if ((uint64_t)L(l) > box.max_label || label_negative(L(l))) bad = true;
+                    else first = true;
                 }
             }
-            g[row * nx + x] = (uint16_t)out;
+            if (x < nx) g[row * nx + x] = (uint16_t)out;
+            if (st[c]) prev_start = c * 64 + 63 - __clzll(st[c]);
+            if (BOX) {
+                const unsigned long long fm = __ballot(first);
+                if (fm) {
+                    const int k = __popcll(fm);
+                    if (nrun + k > XRUNS) {
+                        merge_runs(nrun, z);
+                        nrun = 0;
+                    }
+                    if (first) {
+                        const int at = nrun + __popcll(fm & ((1ull << lane) - 1ull));
+                        runs[3 * at] = l;
+                        runs[3 * at + 1] = (uint32_t)s0;
+                        runs[3 * at + 2] = (uint32_t)e0;
+                    }
+                    nrun += k;
+                }
+            }
         }
+        if (BOX && nrun) merge_runs(nrun, z);
     }
-    __syncthreads();                                     // the masks are reused by the next round
-  }
+    if (__ballot(bad) && lane == 0) atomicOr(err, ERR_LABEL);
     if (BOX) {
+        __syncthreads();
         for (int t = threadIdx.x; t < XBOX_TAB; t += blockDim.x) {
             const uint32_t u = s_key[t];
             if (u == 0u) continue;
             atomicMin(&box.bb[0 * box.nlab + u], s_bb[0][t]);
             atomicMax(&box.bb[1 * box.nlab + u], s_bb[1][t]);
-            atomicMin(&box.bb[2 * box.nlab + u], s_bb[2][t]);
-            atomicMax(&box.bb[3 * box.nlab + u], s_bb[3][t]);
-            atomicMin(&box.bb[4 * box.nlab + u], s_bb[4][t]);
-            atomicMax(&box.bb[5 * box.nlab + u], s_bb[5][t]);
+            atomicMin(&box.bb[2 * box.nlab + u], y);
+            atomicMax(&box.bb[3 * box.nlab + u], y);
+            atomicMin(&box.bb[4 * box.nlab + u], s_bb[2][t]);
+            atomicMax(&box.bb[5 * box.nlab + u], s_bb[3][t]);
         }
     }
 }
@@ -321,16 +360,23 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
     int32_t* d2 = (int32_t*)((char*)scratch + gbytes);
     {
         ProfScope _p(ctx, s, "edt_pass_x");
-        const int threads = min(1024, ((g.nx + 63) / 64) * 64);
-        const int gz = loop_extent(g.nz, g.ny, ctx);
+        const int chunks = (g.nx + 63) / 64;
+        const int gz = loop_extent(g.nz, g.ny, ctx, 4);
         const int zper = (g.nz + gz - 1) / gz;
         const int nzb = (g.nz + zper - 1) / zper;
-        if (box)
-            edt_pass_x<L, true><<<dim3(1, g.ny, nzb), threads, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err, *box,
-                                                                     zper);
-        else
-            edt_pass_x<L, false><<<dim3(1, g.ny, nzb), threads, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err,
-                                                                      BoxTarget{nullptr, 0, 0}, zper);
+        const dim3 grid(1, g.ny, nzb);
+        const BoxTarget nobox{nullptr, 0, 0};
+        auto launch = [&](auto maxc) {
+            constexpr int MC = decltype(maxc)::value;
+            if (box)
+                edt_pass_x<L, true, MC><<<grid, 64 * XW, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err, *box, zper);
+            else
+                edt_pass_x<L, false, MC><<<grid, 64 * XW, 0, s>>>(lab, gx, g.nx, g.ny, g.nz, ctx->d_err, nobox, zper);
+        };
+        if (chunks <= 4) launch(std::integral_constant<int, 4>());
+        else if (chunks <= 8) launch(std::integral_constant<int, 8>());
+        else if (chunks <= 16) launch(std::integral_constant<int, 16>());
+        else launch(std::integral_constant<int, 32>());
     }
     const dim3 lblock(64, 8);
     const int bx = (g.nx + 63) / 64;
