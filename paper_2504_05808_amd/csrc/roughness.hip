@@ -48,16 +48,29 @@ rough_x(const L* __restrict__ lab, const int32_t* __restrict__ D, const int32_t*
     const int x0 = blockIdx.x * RF_XSEG;
     const int seg = min(RF_XSEG, nx - x0);
     const size_t rb = (size_t)row * nx;
-    for (int k = lane; k < seg + 2 * w; k += 64) {
-        const int x = x0 - w + k;
-        uint32_t l = 0u;
-        int32_t f = 0;
-        if (x >= 0 && x < nx) {
-            l = (uint32_t)lab[rb + x];
-            if (l != 0u && D[rb + x] == 1) f = lt[rb + x];
+    // the segment's labels first, then D and LT of its object voxels, all loads of a
+    // stage in flight together
+    constexpr int KX = (RF_XSEG + 2 * RF_MAXW + 63) / 64;
+    uint32_t lv[KX];
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+        const int k = lane + 64 * q, x = x0 - w + k;
+        lv[q] = (k < seg + 2 * w && x >= 0 && x < nx) ? (uint32_t)lab[rb + x] : 0u;
+    }
+    int32_t dv[KX], tv[KX];
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+        const int x = x0 - w + lane + 64 * q;
+        dv[q] = lv[q] != 0u ? D[rb + x] : 0;
+        tv[q] = lv[q] != 0u ? lt[rb + x] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < KX; ++q) {
+        const int k = lane + 64 * q;
+        if (k < seg + 2 * w) {
+            s_l[wv][k] = lv[q];
+            s_f[wv][k] = dv[q] == 1 ? tv[q] : 0;
         }
-        s_l[wv][k] = l;
-        s_f[wv][k] = f;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -149,7 +162,22 @@ rough_line(const L* __restrict__ lab, const int32_t* __restrict__ fin, const int
         s_f[k][lane] = f;
     }
     __syncthreads();
-    for (int k = wv; k < RF_T; k += 4) {
+    // final pass: D and LT of this wave's positions, fetched before the reduction
+    constexpr int KF = RF_T / 4;
+    int32_t dfin[KF], tfin[KF];
+    if (FINAL) {
+#pragma unroll
+        for (int q = 0; q < KF; ++q) {
+            const int k = wv + 4 * q, t = t0 + k;
+            const bool in = xin && t < n_line && s_l[k + w][lane] != 0u;
+            const size_t i = base + (size_t)t * stride;
+            dfin[q] = in ? D[i] : 0;
+            tfin[q] = in ? lt[i] : 0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KF; ++q) {
+        const int k = wv + 4 * q;
         const int t = t0 + k;
         const bool in = xin && t < n_line;
         const uint32_t me = in ? s_l[k + w][lane] : 0u;
@@ -168,13 +196,12 @@ rough_line(const L* __restrict__ lab, const int32_t* __restrict__ fin, const int
             atomicOr(err, ERR_LABEL);
             continue;
         }
-        const size_t i = base + (size_t)t * stride;
         if (me != run.l) {
             rough_merge(s_key, s_shc, s_ssq, s_mx, sums, run);
             run = RoughRun{me, 0ull, 0ull, 0};
         }
-        run.mx = max(run.mx, lt[i]);
-        if (D[i] == 1) {
+        run.mx = max(run.mx, tfin[q]);
+        if (dfin[q] == 1) {
             ++run.shc;
             run.ssq += radius_q23(best);
         }
