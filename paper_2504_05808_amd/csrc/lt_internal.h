@@ -17,7 +17,8 @@ namespace lt {
 enum : uint32_t { ERR_LABEL = 1u, ERR_OVERFLOW = 2u };
 
 // Largest squared radius covered by the exact containment-prune tables.  Centres
-// with a larger D are kept without testing (always exact, only less pruning).
+// with a larger D are tested against the containment bound (prune_bound), which
+// keeps a few more centres than the table would (always exact).
 constexpr int PRUNE_DCAP = 16384;
 
 // Paint tile: up to TILE_Y_MAX target rows x TILE_X columns per work item (columns
@@ -36,9 +37,10 @@ constexpr int ROW_MAX_CHUNKS = 32;
 // Packed z-front entry (3D): bits 0..18 D of the centre, 19..28 dz + 512 (dz is
 // the slice minus the centre's z), 29..31 (plane 0 only) number of entries.  The
 // count 7 marks a front longer than ZF_PLANES: with ZF_SPILL set, bits 16..23 hold
-// its length and bits 0..15 its offset in the spill region of the front pass's
-// block (row of 64 columns, z chunk) that owns the voxel; without it, the column is
-// rescanned.
+// its length and either (ZF_POOL clear) bits 0..15 its offset in the spill region of
+// the front pass's block (row of 64 columns, z chunk) that owns the voxel, or
+// (ZF_POOL set) plane 1 its offset in the shared spill pool; without ZF_SPILL the
+// column is rescanned.
 constexpr uint32_t ZF_D_BITS = 19;
 constexpr uint32_t ZF_D_MASK = (1u << ZF_D_BITS) - 1u;
 constexpr uint32_t ZF_DZ_SHIFT = 19;
@@ -46,9 +48,20 @@ constexpr uint32_t ZF_DZ_MASK = 1023u;
 constexpr uint32_t ZF_N_SHIFT = 29;
 constexpr int ZF_PLANES = 4;
 constexpr uint32_t ZF_SPILL = 1u << 28;
+constexpr uint32_t ZF_POOL = 1u << 24;
+constexpr int ZF_LONG_MAX = 255;               // longest front the 8-bit length holds
 // Spill words per (row of 64 columns, slice) of the front pass: half a word per
-// voxel; a block whose long fronts need more falls back to rescans.
+// voxel; a block whose long fronts need more takes them from the shared pool.
 constexpr int SPILL_ROW_SLICE = 32;
+
+// Shared spill pool of the front passes (one word per voxel): long fronts that do
+// not fit their block's region.  `used` counts requested words (64-bit: requests go
+// on after the pool is full); a front that does not fit is rescanned instead.
+struct SpillPool {
+    uint32_t* base;
+    unsigned long long* used;
+    unsigned long long cap;
+};
 
 // Column-list entry (3D): (D << 11) | z.
 constexpr uint32_t CL_Z_BITS = 11;
@@ -273,6 +286,21 @@ __device__ __forceinline__ int open_reach_w(int b, int w) {
     if (w * h * h >= b) --h;
     else if (w * (h + 1) * (h + 1) < b) ++h;
     return h;
+}
+
+// Containment bound for squared radii beyond the prune tables: for the lattice ball
+// of squared radius d (points with |q|^2 <= d - 1) and an offset of squared length
+// k, max |q - o|^2 <= (sqrt(d - 1) + sqrt(k))^2 <= d - 1 + k + ceil(2 sqrt(k (d - 1))).
+// A neighbour whose D exceeds this contains the ball, so dropping on it is exact
+// (T[d] never exceeds the bound).  The product is taken in 64 bits: weighted 2D
+// distances reach 2^24 with k up to 510.
+__device__ __forceinline__ int prune_bound(int d, int k) {
+    const long long s = 4ll * k * (d - 1);
+    long long r = (long long)__dsqrt_rn((double)s);    // ceil(sqrt(s)), exact after fix-ups
+    if (r * r > s) --r;
+    else if ((r + 1) * (r + 1) <= s) ++r;
+    if (r * r < s) ++r;
+    return d - 1 + k + (int)r;
 }
 
 template <typename L>

@@ -34,11 +34,13 @@ namespace lt {
 
 // ------------------------------------------------------------------ small kernels
 
-__global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uint32_t* gmax, int32_t* colmax,
+// counter words: [0] paint work items (set by plan_tiles), [1] largest D, [2] long-list
+// work items, [3] long-list items taken, [4..5] spill pool words requested (64-bit).
+__global__ void init_label_arrays(int32_t* bb, int32_t* maxd, uint32_t nlab, uint32_t* counter, int32_t* colmax,
                                   size_t ncol) {
     const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
     for (size_t c = l; c < ncol; c += (size_t)gridDim.x * blockDim.x) colmax[c] = 0;
-    if (l == 0) *gmax = 0u;
+    if (l < 5) counter[1 + l] = 0u;
     if (l >= nlab) return;
     if (bb) init_box(bb, nlab, l);
     maxd[l] = 0;
@@ -211,7 +213,8 @@ template <typename L, bool W = false>
 __global__ void __launch_bounds__(PR_NT)
 prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny, int nz,
         uint32_t max_label, const int32_t* __restrict__ tab, int32_t* __restrict__ kd,
-        int32_t* __restrict__ lt, int32_t* __restrict__ maxd, int32_t* __restrict__ colmax, uint32_t* err) {
+        int32_t* __restrict__ lt, int32_t* __restrict__ maxd, int32_t* __restrict__ colmax, uint32_t* err,
+        int wz = 1, int wy = 1, int wx = 1) {
     // a block walks PR_ZB consecutive slices of a 64 x PR_TY tile; D of the slices
     // below, at and above the current one (tile + 1 voxel halo) rotate through LDS
     __shared__ int32_t s_d[3][PR_H][PR_W];
@@ -271,8 +274,12 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
         if (d > 0) {
             const L raw = lab[i];
             keep = true;
-            if (d <= PRUNE_DCAP && !W) {
-                const int a1 = tab[d], a2 = tab[(PRUNE_DCAP + 1) + d], a3 = tab[2 * (PRUNE_DCAP + 1) + d];
+            if (!W) {
+                // thresholds from the tables, or beyond them the containment bound
+                const bool in_tab = d <= PRUNE_DCAP;
+                const int a1 = in_tab ? tab[d] : prune_bound(d, 1);
+                const int a2 = in_tab ? tab[(PRUNE_DCAP + 1) + d] : prune_bound(d, 2);
+                const int a3 = in_tab ? tab[2 * (PRUNE_DCAP + 1) + d] : prune_bound(d, 3);
                 // largest D over the face, edge and corner neighbours: the centre is
                 // dropped when one class exceeds its table value
                 int m1 = 0, m2 = 0, m3 = 0;
@@ -292,7 +299,7 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
                         }
                 }
                 keep = m1 <= a1 && m2 <= a2 && m3 <= a3;
-            } else if (d <= PRUNE_DCAP) {
+            } else {
                 // class c = 4 (dz != 0) + 2 (dy != 0) + (dx != 0) - 1
                 int mc[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -307,8 +314,13 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
                             mc[c] = max(mc[c], s_d[sl][ty + 1 + dy][tx + 1 + dx]);
                         }
                 }
+                const bool in_tab = d <= PRUNE_DCAP;
 #pragma unroll
-                for (int c = 0; c < 7; ++c) keep &= mc[c] <= tab[c * (PRUNE_DCAP + 1) + d];
+                for (int c = 0; c < 7; ++c) {
+                    const int b = c + 1;                      // squared weighted length of the class offset
+                    const int kw = ((b >> 2) & 1) * wz + ((b >> 1) & 1) * wy + (b & 1) * wx;
+                    keep &= mc[c] <= (in_tab ? tab[c * (PRUNE_DCAP + 1) + d] : prune_bound(d, kw));
+                }
             }
             if (keep && d > (int)ZF_D_MASK) atomicOr(err, ERR_OVERFLOW);
             if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;   // flagged elsewhere
@@ -371,12 +383,13 @@ static size_t fronts3d_lds(int chunk) {
 // appended.  Entries come four at a time (LDS broadcasts); four that no lane takes
 // cost one test.  dq[i] holds the D of entry
 // 4 i + 3; the wave stops once no lane has maxb below it.  Members go to p, newest first, or with
-// SPILL to out[0..k).  Returns the front length k.
+// SPILL to out[0..k).  Returns the front length k; vtop gets the D of the first
+// member (the largest of the front).
 // With W the residual is v - wz (z - zc)^2: A = v - wz zc^2, t = A + 2 wz z zc and the
 // threshold maxb + wz z^2 (full 32-bit products).
 template <bool SPILL, bool W = false>
 __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int cnt4, int z, bool act,
-                                          uint32_t (&p)[ZF_PLANES], uint32_t* out, int wz = 1) {
+                                          uint32_t (&p)[ZF_PLANES], uint32_t* out, int& vtop, int wz = 1) {
     const int z2 = W ? 2 * wz * z : 2 * z, zsq = W ? wz * z * z : __mul24(z, z);
     int mz = act ? zsq : INT_MAX;
     int k = 0, lastv = 0;                 // front length, D of the last member
@@ -404,6 +417,7 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
                         for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = app ? p[q - 1] : p[q];
                         p[0] = em ? w : p[0];
                     }
+                    vtop = (em && k == 0) ? v : vtop;
                     k += app ? 1 : 0;
                     lastv = em ? v : lastv;
                     mz = em ? t[u] : mz;
@@ -413,6 +427,33 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
         more = __ballot(mz < d4 + zsq) != 0ull;   // maxb below the D of the fourth
     }
     return k;
+}
+
+// Pool space for the lanes with `need` (a front of m words each) that found no room
+// in their block's region: one global atomic per wave; a lane whose front fits sets
+// at (word offset in the pool) and where = 2.  Called by the whole wave.
+__device__ __forceinline__ void pool_take(const SpillPool& pool, bool need, int m, int lane, uint32_t& at,
+                                          int& where) {
+    if (!__ballot(need)) return;
+    const int want = need ? m : 0;
+    const int incl = wave_scan_add(want);
+    const int tot = __builtin_amdgcn_readlane(incl, 63);
+    unsigned long long b = 0ull;
+    if (lane == 0) b = atomicAdd(pool.used, (unsigned long long)tot);
+    b = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32) |
+        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const unsigned long long mine = b + (unsigned long long)(incl - want);
+    if (need && mine + (unsigned long long)m <= pool.cap) {
+        at = (uint32_t)mine;
+        where = 2;
+    }
+}
+
+// Plane-0 word of a front longer than ZF_PLANES: spilled (block region or pool) or,
+// with no spill space or more members than the length field holds, rescan.
+__device__ __forceinline__ uint32_t long_front_word(int m, uint32_t at, int where) {
+    if (where == 0 || m > ZF_LONG_MAX) return 7u << ZF_N_SHIFT;
+    return (7u << ZF_N_SHIFT) | ZF_SPILL | ((uint32_t)m << 16) | (where == 2 ? ZF_POOL : at);
 }
 
 // One block per (row y, 64 columns, chunk of `chunk` slices), four waves.  Each
@@ -426,16 +467,20 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
 // its largest residual when that exceeds every residual of larger D; slices no
 // listed ball reaches take no part.  A front of up to ZF_PLANES members goes to the
 // planes (plane 0 through an LDS tile, written out coalesced along x); a longer one
-// is written whole to the block's spill region (second scan).  A list longer than
-// FZ_CAP, or a full spill region, marks the fronts "rescan" (count 7 without
-// ZF_SPILL): the paint pass then takes every centre of the column (same result).
+// is written whole to the block's spill region, or when that is full to the shared
+// pool (second scan).  A list longer than FZ_CAP goes to the work list of the
+// long-list pass (fronts3d_long), which overwrites the column's slices of the chunk;
+// a front that finds no spill space is marked "rescan" (count 7 without ZF_SPILL):
+// the paint pass then takes every centre of the column (same result).
 template <bool WG = false>
 __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill,
-         int wz = 1) {
+         uint32_t* __restrict__ work, uint32_t* __restrict__ nwork, uint32_t wcap, SpillPool pool,
+         uint32_t* __restrict__ bmap, int wz = 1) {
     extern __shared__ __align__(16) uint32_t S[];
     __shared__ int s_cm[64];
+    __shared__ int s_bm[128];                         // per slice: largest D of the block's fronts
     __shared__ uint32_t s_used;                       // words of the block's spill region in use
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);    // wave-uniform, in a scalar register
@@ -449,6 +494,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
         s_cm[lane] = lane < W ? colmax[rowi + lane] : 0;
         if (lane == 0) s_used = 0u;
     }
+    if (tid < 128) s_bm[tid] = 0;
     __syncthreads();
     const int zs = c0;                                // first slice of the output tile
     uint32_t* tile = S + 4 * FZ_WAVE;
@@ -490,8 +536,15 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
                 cnt += __popcll(m);
             }
         }
-        if (cnt > FZ_CAP) {
-            for (int z = c0 + lane; z < c1; z += 64) out[(z - zs) * FZ_STRIDE] = 7u << ZF_N_SHIFT;
+        if (cnt > FZ_CAP) {                           // the long-list pass takes the column
+            if (lane == 0) {
+                const uint32_t k = atomicAdd(nwork, 1u);
+                if (k < wcap) work[k] = ((uint32_t)blockIdx.z << 20) | (uint32_t)col;
+            }
+            for (int z = c0 + lane; z < c1; z += 64) {
+                out[(z - zs) * FZ_STRIDE] = 7u << ZF_N_SHIFT;
+                atomicMax(&s_bm[z - c0], cm);         // bound for the long-list pass's fronts
+            }
             continue;
         }
         if (lane < 4) list[cnt + lane] = 0u;          // padding: keys 0 count for no entry
@@ -547,25 +600,31 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             uint32_t p[ZF_PLANES];
 #pragma unroll
             for (int q = 0; q < ZF_PLANES; ++q) p[q] = 0u;
-            int m = 0;
+            int m = 0, vtop = 0, vdummy = 0;
             uint32_t at = 0;
-            bool fits = false;
+            int where = 0;                            // long front: 1 block region, 2 pool, 0 rescan
             if (__ballot(live)) {
-                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, wz);
+                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, vtop, wz);
                 if (m > ZF_PLANES) {
                     at = atomicAdd(&s_used, (uint32_t)m);
-                    fits = at + (uint32_t)m <= cap;   // else: rescan instead
+                    where = at + (uint32_t)m <= cap ? 1 : 0;
                 }
-                const bool again = m > ZF_PLANES && fits;   // second scan: the whole front to the spill
-                if (__ballot(again)) front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p, region + at, wz);
+                pool_take(pool, m > ZF_PLANES && where == 0, m, lane, at, where);
+                const bool again = where != 0;        // second scan: the whole front to the spill
+                if (__ballot(again))
+                    front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p,
+                                         (where == 2 ? pool.base : region) + at, vdummy, wz);
             }
             if (z < c1) {
                 uint32_t w0;
+                const size_t i = (size_t)z * plane + col;
+                // a rescanned column may paint any of its kept centres: bound by the column's largest
+                if (m > 0) atomicMax(&s_bm[z - c0], m > ZF_PLANES && where == 0 ? cm : vtop);
                 if (m > ZF_PLANES) {
-                    w0 = fits ? (7u << ZF_N_SHIFT) | ZF_SPILL | ((uint32_t)m << 16) | at : 7u << ZF_N_SHIFT;
+                    w0 = long_front_word(m, at, where);
+                    if (where == 2) zf[n + i] = at;
                 } else {
                     w0 = m ? (p[0] | ((uint32_t)m << ZF_N_SHIFT)) : 0u;
-                    const size_t i = (size_t)z * plane + col;
 #pragma unroll
                     for (int q = 1; q < ZF_PLANES; ++q)
                         if (m > q) zf[q * n + i] = p[q];
@@ -577,6 +636,139 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     __syncthreads();
     for (int q = wid; q < c1 - c0; q += 4)
         if (lane < W) zf[(size_t)(c0 + q) * plane + rowi + lane] = tile[q * FZ_STRIDE + lane];
+    for (int q = tid; q < c1 - c0; q += 256)
+        bmap[((size_t)(c0 + q) * ny + y) * gridDim.x + blockIdx.x] = (uint32_t)s_bm[q];
+}
+
+// Columns whose list outgrew FZ_CAP: the same fronts from a per-wave list that holds
+// a whole column (FZ_BIG >= the largest extent), 16 entries per lane.  A persistent
+// grid; each wave takes (chunk << 20 | column) items from the front pass's work list
+// and rewrites that column's plane-0 words of the chunk (one word per slice, so the
+// writes are not coalesced: these columns are few).  Long fronts go to the pool.
+constexpr int FZ_BIG = 1024;
+constexpr int FZ_BIG_E = FZ_BIG / 64;                // entries per lane
+constexpr int FZ_BIG_WAVE = 2 * (FZ_BIG + 4) + FZ_BIG / 4;
+
+static size_t fronts3d_long_lds() { return (size_t)4 * FZ_BIG_WAVE * sizeof(uint32_t); }
+
+template <bool WG = false>
+__global__ void __launch_bounds__(256)
+fronts3d_long(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
+              const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, const uint32_t* __restrict__ work,
+              const uint32_t* __restrict__ nwork, uint32_t wcap, uint32_t* __restrict__ take, SpillPool pool,
+              int wz = 1) {
+    extern __shared__ __align__(16) uint32_t S[];
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* list = S + wid * FZ_BIG_WAVE;
+    int* dq = (int*)(list + 2 * (FZ_BIG + 4));
+    const size_t plane = (size_t)ny * nx;
+    const size_t n = plane * nz;
+    const uint32_t total = min(*nwork, wcap);        // final: the front pass has ended
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (;;) {
+        uint32_t it = 0u;
+        if (lane == 0) it = atomicAdd(take, 1u);
+        it = (uint32_t)__builtin_amdgcn_readfirstlane((int)it);
+        if (it >= total) break;
+        const uint32_t item = work[it];
+        const size_t col = item & 0xfffffu;
+        const int c0 = (int)(item >> 20) * chunk, c1 = min(nz, c0 + chunk);
+        const int cm = colmax[col];
+        const int R = WG ? open_reach_w(cm, wz) : open_reach(cm);
+        const int lo = max(0, c0 - R), hi = min(nz, c1 + R);
+        const int32_t* kcol = kd + col * (size_t)nz;
+        int cnt = 0;                                  // <= hi - lo <= nz <= FZ_BIG
+        for (int zb = lo; zb < hi; zb += 64) {
+            const int z = zb + lane;
+            const int v = z < hi ? kcol[z] : 0;
+            const int d = max(max(c0 - z, z - (c1 - 1)), 0);
+            const bool keep = v > (WG ? wz * d * d : __mul24(d, d));
+            const unsigned long long m = __ballot(keep);
+            if (keep) list[cnt + __popcll(m & below)] = ((uint32_t)v << CL_Z_BITS) | (uint32_t)z;
+            cnt += __popcll(m);
+        }
+        if (lane < 4) list[cnt + lane] = 0u;
+        wave_lds_sync();
+        const int nh = (cnt + 63) >> 6;               // wave-uniform: entries held per lane
+        uint32_t e[FZ_BIG_E];
+        int r[FZ_BIG_E];
+#pragma unroll
+        for (int h = 0; h < FZ_BIG_E; ++h) {
+            e[h] = lane + 64 * h < cnt ? list[lane + 64 * h] : 0u;
+            r[h] = 0;
+        }
+        for (int k = 0; k < cnt; k += 4) {
+            const uint4 q = *(const uint4*)(list + k);
+#pragma unroll
+            for (int h = 0; h < FZ_BIG_E; ++h)
+                if (h < nh) r[h] += (q.x > e[h]) + (q.y > e[h]) + (q.z > e[h]) + (q.w > e[h]);
+        }
+        const int cnt4 = (cnt + 3) & ~3;
+        uint2* ent = (uint2*)list;
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < FZ_BIG_E; ++h) {
+            if (lane + 64 * h < cnt) {
+                const int zc = (int)(e[h] & CL_Z_MASK), v = (int)(e[h] >> CL_Z_BITS);
+                ent[r[h]] = make_uint2((uint32_t)zc, (uint32_t)(v - (WG ? wz : 1) * zc * zc));
+                if ((r[h] & 3) == 3) dq[r[h] >> 2] = v;
+            }
+        }
+        if (lane < cnt4 - cnt) {
+            ent[cnt + lane] = make_uint2(0u, 0xc0000000u);
+            if (((cnt + lane) & 3) == 3) dq[(cnt + lane) >> 2] = INT_MIN / 2;
+        }
+        wave_lds_sync();
+        for (int zr = c0; zr < c1; zr += 64) {
+            unsigned long long cov = 0ull;
+#pragma unroll
+            for (int h = 0; h < FZ_BIG_E; ++h) {
+                if (lane + 64 * h < cnt) {
+                    const int ev = (int)(e[h] >> CL_Z_BITS);
+                    const int rr = WG ? open_reach_w(ev, wz) : open_reach(ev), zc = (int)(e[h] & CL_Z_MASK);
+                    const int a = max(zc - rr, zr) - zr, b = min(zc + rr, zr + 63) - zr;
+                    if (a <= b) {
+                        const int len = b - a + 1;
+                        cov |= (len == 64 ? ~0ull : ((1ull << len) - 1ull)) << a;
+                    }
+                }
+            }
+            const uint32_t clo = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_or((uint32_t)cov), 63);
+            const uint32_t chi = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_or((uint32_t)(cov >> 32)), 63);
+            const int z = zr + lane;
+            const bool live = z < c1 && (((lane < 32 ? clo >> lane : chi >> (lane - 32)) & 1u) != 0u);
+            uint32_t p[ZF_PLANES];
+#pragma unroll
+            for (int q = 0; q < ZF_PLANES; ++q) p[q] = 0u;
+            int m = 0;
+            uint32_t at = 0;
+            int where = 0;
+            if (__ballot(live)) {
+                int vd = 0;                           // the group bound is the column's largest D
+                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, vd, wz);
+                pool_take(pool, m > ZF_PLANES && m <= ZF_LONG_MAX, m, lane, at, where);
+                const bool again = where != 0;
+                if (__ballot(again))
+                    front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p, pool.base + at, vd, wz);
+            }
+            if (z < c1) {
+                const size_t i = (size_t)z * plane + col;
+                uint32_t w0;
+                if (m > ZF_PLANES) {
+                    w0 = long_front_word(m, at, where);
+                    if (where == 2) zf[n + i] = at;
+                } else {
+                    w0 = m ? (p[0] | ((uint32_t)m << ZF_N_SHIFT)) : 0u;
+#pragma unroll
+                    for (int q = 1; q < ZF_PLANES; ++q)
+                        if (m > q) zf[q * n + i] = p[q];
+                }
+                zf[i] = w0;
+            }
+        }
+        wave_lds_sync();                              // the next item reuses the list
+    }
 }
 
 // ------------------------------------------------------------------ 2D pixel pass
@@ -587,7 +779,7 @@ template <typename L, bool W = false>
 __global__ void __launch_bounds__(256)
 pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny,
          uint32_t max_label, const int32_t* __restrict__ tab, uint32_t* __restrict__ zf,
-         int32_t* __restrict__ lt, int32_t* __restrict__ maxd) {
+         int32_t* __restrict__ lt, int32_t* __restrict__ maxd, int wy = 1, int wx = 1) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const size_t i = (size_t)y * nx + x;
@@ -597,9 +789,10 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
     if (d > 0) {
         const L raw = lab[i];
         keep = true;
-        if (d <= PRUNE_DCAP) {
+        {
             // classes: unweighted by |o|^2 (edge, corner); with W by the axes moved
-            // along (c = 2 (dy != 0) + (dx != 0) - 1)
+            // along (c = 2 (dy != 0) + (dx != 0) - 1); thresholds from the tables, or
+            // beyond them the containment bound
             int mc[3] = {0, 0, 0};
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
@@ -612,8 +805,11 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
                     const int c = W ? 2 * (dy != 0) + (dx != 0) - 1 : k - 1;
                     mc[c] = max(mc[c], dn);
                 }
-            keep = mc[0] <= tab[d] && mc[1] <= tab[(PRUNE_DCAP + 1) + d];
-            if (W) keep = keep && mc[2] <= tab[2 * (PRUNE_DCAP + 1) + d];
+            const bool in_tab = d <= PRUNE_DCAP;
+            const int k0 = W ? wx : 1, k1 = W ? wy : 2, k2 = wx + wy;
+            keep = mc[0] <= (in_tab ? tab[d] : prune_bound(d, k0)) &&
+                   mc[1] <= (in_tab ? tab[(PRUNE_DCAP + 1) + d] : prune_bound(d, k1));
+            if (W) keep = keep && mc[2] <= (in_tab ? tab[2 * (PRUNE_DCAP + 1) + d] : prune_bound(d, k2));
         }
         zf[i] = keep ? ((uint32_t)d | 0x80000000u) : 0u;
         if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;
@@ -626,37 +822,61 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
 
 // ------------------------------------------------------------------ planning
 
-// Exclusive scan over labels of the number of paint tiles of each present object.
-// toff has nlab + 1 entries; toff[nlab] is the total.  One block of 1024 threads.
+// Objects whose balls reach at least this far along y or x (3D) are painted by the
+// banded launch: value bands with a tile floor (their source region spans several
+// tiles' worth of columns).
+constexpr int BAND_REACH = 32;
+constexpr int BAND_ZCHUNK = 16;      // slices per banded work item (a large object alone fills the chip)
+
+// Exclusive scans over labels of the number of paint items of each present object,
+// split by size: objects whose largest D exceeds band_d (balls reaching BAND_REACH or
+// more along y or x) go to toff_big and the banded paint launch, one item per (tile,
+// BAND_ZCHUNK slices); the rest to toff, one item per tile over all its slices.
+// toff and toff_big have nlab + 1 entries; entry nlab is the total.  One block of
+// 1024 threads.
 __global__ void __launch_bounds__(1024)
-plan_tiles(const int32_t* __restrict__ bb, uint32_t nlab, int tile_y, uint32_t* __restrict__ toff,
+plan_tiles(const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd, uint32_t nlab, int tile_y,
+           int band_d, uint32_t* __restrict__ toff, uint32_t* __restrict__ toff_big,
            uint32_t* __restrict__ counter) {
-    __shared__ uint32_t s[1024];
+    __shared__ uint32_t s[2][1024];
     const int t = threadIdx.x;
-    uint32_t running = 0;
+    uint32_t running[2] = {0u, 0u};
     for (uint32_t base = 0; base < nlab; base += 1024) {
         const uint32_t l = base + t;
         uint32_t c = 0;
+        bool big = false;
         if (l > 0 && l < nlab && bb[5 * nlab + l] >= 0) {
             const int by = bb[3 * nlab + l] - bb[2 * nlab + l] + 1;
             const int bx = bb[5 * nlab + l] - bb[4 * nlab + l] + 1;
             c = (uint32_t)((by + tile_y - 1) / tile_y) * (uint32_t)((bx + TILE_X - 1) / TILE_X);
+            big = maxd[l] > band_d;
+            if (big) c *= (uint32_t)((bb[1 * nlab + l] - bb[0 * nlab + l] + BAND_ZCHUNK) / BAND_ZCHUNK);
         }
-        s[t] = c;
+        const uint32_t cs[2] = {big ? 0u : c, big ? c : 0u};
+        s[0][t] = cs[0];
+        s[1][t] = cs[1];
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t v = t >= off ? s[t - off] : 0u;
+            const uint32_t v0 = t >= off ? s[0][t - off] : 0u;
+            const uint32_t v1 = t >= off ? s[1][t - off] : 0u;
             __syncthreads();
-            s[t] += v;
+            s[0][t] += v0;
+            s[1][t] += v1;
             __syncthreads();
         }
-        if (l < nlab) toff[l] = running + s[t] - c;
-        running += s[1023];
+        if (l < nlab) {
+            toff[l] = running[0] + s[0][t] - cs[0];
+            toff_big[l] = running[1] + s[1][t] - cs[1];
+        }
+        running[0] += s[0][1023];
+        running[1] += s[1][1023];
         __syncthreads();
     }
     if (t == 0) {
-        toff[nlab] = running;
-        *counter = 0;
+        toff[nlab] = running[0];
+        toff_big[nlab] = running[1];
+        counter[0] = 0u;                               // work items of the two paint launches
+        counter[6] = 0u;
     }
 }
 
@@ -836,24 +1056,27 @@ __device__ __forceinline__ void disc_push(const TileCtx& t, int& n, bool has, in
 // span the rows with wy dy^2 < b and intervals the columns with wx dx^2 < b - wy dy^2;
 // the fused shell test reads the face neighbours' labels (D = 1 identifies the
 // shell only at unit spacing).
-template <int NDIM, typename L, bool W = false>
+template <int NDIM, typename L, bool W = false, bool BAND = false>
 __global__ void __launch_bounds__(PAINT_THREADS)
 paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             const int32_t* __restrict__ kd, const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
             const uint32_t* __restrict__ toff, uint32_t nlab, int nx, int ny, int nz, int tile_y,
             uint32_t* __restrict__ counter, int32_t* __restrict__ lt, const uint32_t* __restrict__ spill,
-            int chunk, MeasureSums ms, const int32_t* __restrict__ Dmap, Spacing spc = Spacing()) {
+            const uint32_t* __restrict__ pool, const uint32_t* __restrict__ bmap, int chunk, MeasureSums ms,
+            const int32_t* __restrict__ Dmap, Spacing spc = Spacing()) {
     // dynamic LDS: the sparse table [TILE_LEVELS][tile_y][TILE_STRIDE], then one disc
     // list per wave
     extern __shared__ uint32_t M[];
     __shared__ uint32_t s_item;
     __shared__ unsigned long long s_dirty[2];      // painted rows, by slice parity
+    __shared__ int s_floor[2];                     // tile floors of the banded passes
     __shared__ uint8_t s_reach[REACH_TAB];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int nwaves = blockDim.x >> 6;
     const uint32_t total = toff[nlab];
     const size_t n = (size_t)nx * ny * nz;
+    const int ngroups = (nx + 63) / 64;
     // The table is all zero between slices: every cell a slice uses is cleared by
     // the wave that reads it out.
     for (int q = tid; q < TILE_LEVELS * (tile_y * TILE_STRIDE + 1); q += blockDim.x) M[q] = 0u;
@@ -871,6 +1094,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         if (tid == 0) {
             s_item = atomicAdd(counter, 1u);
             s_dirty[0] = s_dirty[1] = 0ull;
+            s_floor[0] = s_floor[1] = INT_MAX;
         }
         __syncthreads();
         const uint32_t item = s_item;
@@ -893,7 +1117,14 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int Ry = W ? open_reach_w(mdl, spc.wy) : R;
         const int Rx = W ? open_reach_w(mdl, spc.wx) : R;
         const int tiles_x = (x1 - x0 + TILE_X - 1) / TILE_X;
-        const int tt = (int)(item - toff[l]);
+        int tt = (int)(item - toff[l]);
+        int pz0 = NDIM == 3 ? z0 : 0, pz1 = NDIM == 3 ? z1 : 1;
+        if (BAND) {                                  // items of BAND_ZCHUNK slices each
+            const int ntile = tiles_x * ((y1 - y0 + tile_y - 1) / tile_y);
+            pz0 = z0 + (tt / ntile) * BAND_ZCHUNK;
+            pz1 = min(z1, pz0 + BAND_ZCHUNK);
+            tt %= ntile;
+        }
         TileCtx t;
         t.M = M;
         t.disc = (int*)(M + TILE_LEVELS * (tile_y * TILE_STRIDE + 1)) + wid * (4 * DL_CAP + 64);
@@ -907,15 +1138,135 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         t.wx = spc.wx;
         const int sy0 = max(y0, t.ty0 - Ry), sy1 = min(y1, t.ty0 + t.H + Ry);
         const int sx0 = max(x0, t.tx0 - Rx), sx1 = min(x1, t.tx0 + t.W + Rx);
+        // Floor of the tile in slice pz after a band: the table is pushed down to level
+        // 0 (the cells keep their values, the upper levels are cleared, so later bands
+        // paint on), and the smallest value over the object's cells is taken (0 while
+        // one is unpainted; INT_MAX when the slice holds none).
+        auto tile_floor = [&](int slot, int pz) -> int {
+            __syncthreads();                            // every wave's discs are in the table
+            for (int row = wid; row < t.H; row += nwaves) {
+                uint32_t val[TILE_LEVELS];
+#pragma unroll
+                for (int k = 0; k < TILE_LEVELS; ++k)
+                    val[k] = lane < t.W ? t.M[k * t.lstride + row * TILE_STRIDE + lane] : 0u;
+#pragma unroll
+                for (int k = TILE_LEVELS - 1; k >= 1; --k) {
+                    const uint32_t up = (uint32_t)__builtin_amdgcn_ds_bpermute((int)pd_idx[k], (int)val[k]);
+                    val[k - 1] = max(val[k - 1], max(val[k], up));
+                }
+                int mn = INT_MAX;
+                if (lane < t.W) {
+                    t.M[row * TILE_STRIDE + lane] = val[0];
+#pragma unroll
+                    for (int k = 1; k < TILE_LEVELS; ++k) t.M[k * t.lstride + row * TILE_STRIDE + lane] = 0u;
+                    const L lv = lab[((size_t)pz * ny + t.ty0 + row) * nx + t.tx0 + lane];
+                    if ((uint64_t)lv == (uint64_t)l) mn = (int)val[0];
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) mn = min(mn, __shfl_xor(mn, off, 64));
+                if (lane == 0 && mn != INT_MAX) atomicMin(&s_floor[slot], mn);
+            }
+            __syncthreads();
+            return s_floor[slot];
+        };
         // fused measures: this thread's share of the item's volume, radius sums,
         // largest LT and shell terms (every painted cell is a voxel of label l)
         uint32_t a_n = 0, a_sn = 0;
         uint64_t a_q = 0, a_sq = 0;
         int a_mx = 0;
-        for (int pz = (NDIM == 3 ? z0 : 0); pz < (NDIM == 3 ? z1 : 1); ++pz) {
+        for (int pz = pz0; pz < pz1; ++pz) {
             t.dirty = &s_dirty[pz & 1];
             int nlist = 0;                                // listed discs (wave-uniform)
             int sylast = sy0;
+            // Discs of one source column (lane) in this slice: the stored front, the
+            // spilled front or a rescan of the column.  Only discs that reach the
+            // tile (b > need) with a value above the floor fl are listed.
+            auto column = [&](L lc, uint32_t ec, int sx, int sy, size_t rowi, int need, int fl)
+                              __attribute__((always_inline)) {
+                const bool own = sx < sx1 && (uint64_t)lc == (uint64_t)l;
+                const uint32_t e0 = own ? ec : 0u;
+                uint32_t e[ZF_PLANES];
+                e[0] = e0;
+#pragma unroll
+                for (int q = 1; q < ZF_PLANES; ++q) e[q] = 0u;
+                int nent = 0;
+                bool rescan = false, spilled = false;
+                if (NDIM == 2) {
+                    nent = e0 ? 1 : 0;
+                } else if (e0) {
+                    const int cc = (int)(e0 >> ZF_N_SHIFT);
+                    spilled = cc == 7 && (e0 & ZF_SPILL);
+                    rescan = cc == 7 && !spilled;
+                    nent = cc == 7 ? 0 : cc;
+#pragma unroll
+                    for (int q = 1; q < ZF_PLANES; ++q)
+                        if (nent > q) e[q] = zf[q * n + rowi + sx];
+                }
+                // stored front entries
+#pragma unroll
+                for (int p = 0; p < ZF_PLANES; ++p) {
+                    const bool has = p < nent;
+                    if (!__ballot(has)) break;
+                    int v = 0, b = 0;
+                    if (has) {
+                        if (NDIM == 2) {
+                            v = b = (int)(e[p] & 0x7fffffffu);
+                        } else {
+                            v = (int)(e[p] & ZF_D_MASK);
+                            const int dz = (int)((e[p] >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
+                            b = v - (W ? spc.wz : 1) * dz * dz;
+                        }
+                    }
+                    disc_push<NDIM, W>(t, nlist, has && b > need && v > fl, v, b, sx, sy, lane);
+                }
+                // long fronts kept in the front pass's spill region or the pool
+                if (NDIM == 3 && __ballot(spilled)) {
+                    int m = 0;
+                    const uint32_t* sp = spill;
+                    if (spilled) {
+                        m = (int)((e0 >> 16) & 0xffu);
+                        if (e0 & ZF_POOL) {
+                            sp = pool + zf[n + rowi + sx];
+                        } else {
+                            const size_t blk = ((size_t)(pz / chunk) * ny + sy) * ((nx + 63) / 64) + sx / 64;
+                            sp = spill + blk * (size_t)(SPILL_ROW_SLICE * chunk) + (e0 & 0xffffu);
+                        }
+                    }
+                    for (int q = 0; __ballot(q < m); ++q) {
+                        const bool has = q < m;
+                        int v = 0, b = 0;
+                        if (has) {
+                            const uint32_t w = sp[q];
+                            v = (int)(w & ZF_D_MASK);
+                            const int dz = (int)((w >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
+                            b = v - (W ? spc.wz : 1) * dz * dz;
+                        }
+                        disc_push<NDIM, W>(t, nlist, has && b > need && v > fl, v, b, sx, sy, lane);
+                    }
+                }
+                // fronts that did not fit the spill region: every kept centre of the
+                // column (within the object's z range) that reaches this slice -- a
+                // superset of the front.  The wave walks the offsets dz = -R..R
+                // together, four independent loads at a time.
+                if (NDIM == 3 && __ballot(rescan)) {
+                    const size_t col = (size_t)sy * nx + sx;
+                    for (int d0 = -Rz; d0 <= Rz; d0 += 4) {
+                        int kv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int zc = pz + d0 + u;
+                            kv[u] = (rescan && d0 + u <= Rz && zc >= z0 && zc < z1) ? kd[col * (size_t)nz + zc] : 0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int dz = d0 + u;
+                            const int b = kv[u] - (W ? spc.wz : 1) * dz * dz;
+                            disc_push<NDIM, W>(t, nlist, kv[u] > fl && b > 0 && b > need, kv[u], b, sx, sy,
+                                               lane);
+                        }
+                    }
+                }
+            };
             // labels and plane-0 fronts of a whole source row, loaded together; the
             // next row of the wave is fetched while the current one is processed
             constexpr int MAXC = 3;                       // source rows span <= 64 + 2 * 64 columns
@@ -931,127 +1282,110 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     nev[c] = in ? zf[ri + sx] : 0u;
                 }
             };
-            fetch_row(sy0 + wid);
-            for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
-                sylast = sy;
-                L lv[MAXC];
-                uint32_t ev[MAXC];
+            if constexpr (BAND) {
+                // Objects of large reach: the source groups (one source row x 64 columns)
+                // in three bands of their largest front value -- those holding the
+                // object's largest D, those of at least half of it, the rest -- with the
+                // tile's floor (smallest value painted so far over the object's cells in
+                // this slice) taken after the first two.  A group whose largest value
+                // does not exceed the floor, and any disc that does not, cannot raise a
+                // cell and is skipped.
+                const uint32_t* bms = bmap + (size_t)pz * ny * ngroups;
+                int fl = 0;
+                // group maxima of a source row, loaded together BM_CH chunks of 64
+                // columns at a time (one round trip for rows up to 384 columns)
+                constexpr int BM_CH = 6;
+                const int nch = (sx1 - sx0 + 63) >> 6;
+                for (int band = 0; band < 3; ++band) {
+                    const int lo_b = band == 0 ? mdl : band == 1 ? (mdl >> 1) : INT_MIN;
+                    const int hi_b = band == 0 ? INT_MAX : band == 1 ? mdl : (mdl >> 1);
+                    for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
+                        const size_t rowi = ((size_t)pz * ny + sy) * nx;
+                        const int ddy = max(max(t.ty0 - sy, sy - (t.ty0 + t.H - 1)), 0);
+                        const int rowd = W ? spc.wy * ddy * ddy : ddy * ddy;
+                        for (int cb = 0; cb < nch; cb += BM_CH) {
+                            int bmr[BM_CH];
 #pragma unroll
-                for (int c = 0; c < MAXC; ++c) {
-                    lv[c] = nlv[c];
-                    ev[c] = nev[c];
-                }
-                fetch_row(sy + nwaves);
-                const size_t rowi = ((size_t)pz * ny + sy) * nx;
-                for (int c = 0; c * 64 < sx1 - sx0; ++c) {
-                    const int sx = sx0 + c * 64 + lane;
-                    L lc;
-                    uint32_t ec;
-                    if (c == 0) {
-                        lc = lv[0];
-                        ec = ev[0];
-                    } else if (c == 1) {
-                        lc = lv[1];
-                        ec = ev[1];
-                    } else if (c == 2) {
-                        lc = lv[2];
-                        ec = ev[2];
-                    } else {                              // very wide objects only
-                        lc = sx < sx1 ? lab[rowi + sx] : L(0);
-                        ec = sx < sx1 ? zf[rowi + sx] : 0u;
-                    }
-                    const bool own = sx < sx1 && (uint64_t)lc == (uint64_t)l;
-                    const uint32_t e0 = own ? ec : 0u;
-                    uint32_t e[ZF_PLANES];
-                    e[0] = e0;
-#pragma unroll
-                    for (int q = 1; q < ZF_PLANES; ++q) e[q] = 0u;
-                    int nent = 0;
-                    bool rescan = false, spilled = false;
-                    if (NDIM == 2) {
-                        nent = e0 ? 1 : 0;
-                    } else if (e0) {
-                        const int cc = (int)(e0 >> ZF_N_SHIFT);
-                        spilled = cc == 7 && (e0 & ZF_SPILL);
-                        rescan = cc == 7 && !spilled;
-                        nent = cc == 7 ? 0 : cc;
-#pragma unroll
-                        for (int q = 1; q < ZF_PLANES; ++q)
-                            if (nent > q) e[q] = zf[q * n + rowi + sx];
-                    }
-                    // stored front entries
-#pragma unroll
-                    for (int p = 0; p < ZF_PLANES; ++p) {
-                        const bool has = p < nent;
-                        if (!__ballot(has)) break;
-                        int v = 0, b = 0;
-                        if (has) {
-                            if (NDIM == 2) {
-                                v = b = (int)(e[p] & 0x7fffffffu);
-                            } else {
-                                v = (int)(e[p] & ZF_D_MASK);
-                                const int dz = (int)((e[p] >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
-                                b = v - (W ? spc.wz : 1) * dz * dz;
+                            for (int u = 0; u < BM_CH; ++u) {
+                                const int sx = sx0 + (cb + u) * 64 + lane;
+                                bmr[u] = sx < sx1 ? (int)bms[(size_t)sy * ngroups + (sx >> 6)] : 0;
                             }
+                        for (int u = 0; u < BM_CH && cb + u < nch; ++u) {
+                            const int c = cb + u;
+                            const int sx = sx0 + c * 64 + lane;
+                            const bool in = sx < sx1;
+                            int bmv = bmr[0];
+#pragma unroll
+                            for (int q = 1; q < BM_CH; ++q) bmv = u == q ? bmr[q] : bmv;
+                            const bool go = in && bmv >= lo_b && bmv < hi_b && bmv > fl;
+                            if (!__ballot(go)) continue;
+                            const int ddx = max(max(t.tx0 - sx, sx - (t.tx0 + t.W - 1)), 0);
+                            const int need = rowd + (W ? spc.wx * ddx * ddx : ddx * ddx);
+                            const L lc = go ? lab[rowi + sx] : L(0);
+                            const uint32_t ec = go ? zf[rowi + sx] : 0u;
+                            column(lc, ec, sx, sy, rowi, need, fl);
                         }
-                        disc_push<NDIM, W>(t, nlist, has, v, b, sx, sy, lane);
-                    }
-                    // long fronts kept in the front pass's spill region
-                    if (NDIM == 3 && __ballot(spilled)) {
-                        int m = 0;
-                        const uint32_t* sp = spill;
-                        if (spilled) {
-                            m = (int)((e0 >> 16) & 0xffu);
-                            const size_t blk = ((size_t)(pz / chunk) * ny + sy) * ((nx + 63) / 64) + sx / 64;
-                            sp = spill + blk * (size_t)(SPILL_ROW_SLICE * chunk) + (e0 & 0xffffu);
-                        }
-                        for (int q = 0; __ballot(q < m); ++q) {
-                            const bool has = q < m;
-                            int v = 0, b = 0;
-                            if (has) {
-                                const uint32_t w = sp[q];
-                                v = (int)(w & ZF_D_MASK);
-                                const int dz = (int)((w >> ZF_DZ_SHIFT) & ZF_DZ_MASK) - 512;
-                                b = v - (W ? spc.wz : 1) * dz * dz;
-                            }
-                            disc_push<NDIM, W>(t, nlist, has, v, b, sx, sy, lane);
                         }
                     }
-                    // fronts that did not fit the spill region: every kept centre of the
-                    // column (within the object's z range) that reaches this slice -- a
-                    // superset of the front.  The wave walks the offsets dz = -R..R
-                    // together, four independent loads at a time.
-                    if (NDIM == 3 && __ballot(rescan)) {
-                        const size_t col = (size_t)sy * nx + sx;
-                        for (int d0 = -Rz; d0 <= Rz; d0 += 4) {
-                            int kv[4];
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int zc = pz + d0 + u;
-                                kv[u] = (rescan && d0 + u <= Rz && zc >= z0 && zc < z1) ? kd[col * (size_t)nz + zc] : 0;
-                            }
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int dz = d0 + u;
-                                const int b = kv[u] - (W ? spc.wz : 1) * dz * dz;
-                                disc_push<NDIM, W>(t, nlist, kv[u] > 0 && b > 0, kv[u], b, sx, sy, lane);
-                            }
-                        }
-                    }
-                }
-                if (NDIM == 2 && nlist) {                 // 2D lists hold one source row
-                    disc_flush<NDIM, W>(t, nlist, sy, lane);
+                    if (nlist) disc_flush<NDIM, W>(t, nlist, sy0, lane);
                     nlist = 0;
+                    if (band < 2) fl = tile_floor(band, pz);
                 }
+            } else {
+                fetch_row(sy0 + wid);
+                for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
+                    sylast = sy;
+                    L lv[MAXC];
+                    uint32_t ev[MAXC];
+#pragma unroll
+                    for (int c = 0; c < MAXC; ++c) {
+                        lv[c] = nlv[c];
+                        ev[c] = nev[c];
+                    }
+                    fetch_row(sy + nwaves);
+                    const size_t rowi = ((size_t)pz * ny + sy) * nx;
+                    // a disc of residual b reaches a tile cell only if b exceeds the squared
+                    // distance from its centre to the tile: discs below it are not listed
+                    const int ddy = max(max(t.ty0 - sy, sy - (t.ty0 + t.H - 1)), 0);
+                    const int rowd = W ? spc.wy * ddy * ddy : ddy * ddy;
+                    for (int c = 0; c * 64 < sx1 - sx0; ++c) {
+                        const int sx = sx0 + c * 64 + lane;
+                        const int ddx = max(max(t.tx0 - sx, sx - (t.tx0 + t.W - 1)), 0);
+                        const int need = rowd + (W ? spc.wx * ddx * ddx : ddx * ddx);
+                        L lc;
+                        uint32_t ec;
+                        if (c == 0) {
+                            lc = lv[0];
+                            ec = ev[0];
+                        } else if (c == 1) {
+                            lc = lv[1];
+                            ec = ev[1];
+                        } else if (c == 2) {
+                            lc = lv[2];
+                            ec = ev[2];
+                        } else {                              // very wide objects only
+                            lc = sx < sx1 ? lab[rowi + sx] : L(0);
+                            ec = sx < sx1 ? zf[rowi + sx] : 0u;
+                        }
+                        column(lc, ec, sx, sy, rowi, need, 0);
+                    }
+                    if (NDIM == 2 && nlist) {                 // 2D lists hold one source row
+                        disc_flush<NDIM, W>(t, nlist, sy, lane);
+                        nlist = 0;
+                    }
+                }
+                if (nlist) disc_flush<NDIM, W>(t, nlist, sylast, lane);
             }
-            if (nlist) disc_flush<NDIM, W>(t, nlist, sylast, lane);
             __syncthreads();
             // push-down of the sparse table, one wave per painted row: level k-1 at
             // column c takes the blocks of level k starting at c and c - 2^(k-1); then
             // write the painted cells and clear every level of the row.  Rows no disc
             // reached are still clear and hold no voxel of the object.
             const unsigned long long painted = *t.dirty;
-            if (tid == 0) s_dirty[(pz + 1) & 1] = 0ull;   // the next slice's mask
+            if (tid == 0) {
+                s_dirty[(pz + 1) & 1] = 0ull;             // the next slice's mask
+                s_floor[0] = s_floor[1] = INT_MAX;        // read before the last band
+            }
             for (int row = wid; row < t.H; row += nwaves) {
                 if (!((painted >> row) & 1ull)) continue;
                 // levels above floor(log2(min(W, 2R + 1))) are never painted and hold
@@ -1132,7 +1466,9 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
 static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct ThickLayout {
-    size_t bb, maxd, toff, counter, zf, kd, spill, colmax, total;
+    size_t bb, maxd, toff, toff_big, counter, zf, kd, spill, colmax, work, pool, bmap, total;
+    uint32_t wcap;          // long-list work items: one per (column, chunk) at the smallest chunk
+    size_t pool_words;
 };
 
 static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
@@ -1142,6 +1478,7 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.bb = at;      at += align256(6 * nlab * sizeof(int32_t));
     o.maxd = at;    at += align256(nlab * sizeof(int32_t));
     o.toff = at;    at += align256((nlab + 1) * sizeof(uint32_t));
+    o.toff_big = at; at += align256((nlab + 1) * sizeof(uint32_t));
     o.counter = at; at += 256;
     o.zf = at;      at += align256((g.ndim == 3 ? ZF_PLANES : 1) * g.n * sizeof(uint32_t));
     o.kd = at;      at += g.ndim == 3 ? align256(g.n * sizeof(int32_t)) : 0;
@@ -1152,6 +1489,12 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
                                  sizeof(uint32_t))
                       : 0;
     o.colmax = at;  at += g.ndim == 3 ? align256((size_t)g.ny * g.nx * sizeof(int32_t)) : 0;
+    o.wcap = g.ndim == 3 ? (uint32_t)((size_t)g.ny * g.nx * ((g.nz + 31) / 32)) : 0u;
+    o.work = at;    at += align256((size_t)o.wcap * sizeof(uint32_t));
+    o.pool_words = g.ndim == 3 ? g.n : 0;
+    o.pool = at;    at += align256(o.pool_words * sizeof(uint32_t));
+    // largest front value per (slice, row, 64-column group)
+    o.bmap = at;    at += g.ndim == 3 ? align256((size_t)g.nz * g.ny * ((g.nx + 63) / 64) * sizeof(uint32_t)) : 0;
     o.total = at;
     return o;
 }
@@ -1181,7 +1524,13 @@ int paint_tile_rows(lt_ctx* ctx) {
                              (const void*)paint_tiles<2, int32_t>, (const void*)paint_tiles<2, uint32_t>,
                              (const void*)paint_tiles<3, uint16_t, true>, (const void*)paint_tiles<3, int32_t, true>,
                              (const void*)paint_tiles<3, uint32_t, true>, (const void*)paint_tiles<2, uint16_t, true>,
-                             (const void*)paint_tiles<2, int32_t, true>, (const void*)paint_tiles<2, uint32_t, true>};
+                             (const void*)paint_tiles<2, int32_t, true>, (const void*)paint_tiles<2, uint32_t, true>,
+                             (const void*)paint_tiles<3, uint16_t, false, true>,
+                             (const void*)paint_tiles<3, int32_t, false, true>,
+                             (const void*)paint_tiles<3, uint32_t, false, true>,
+                             (const void*)paint_tiles<3, uint16_t, true, true>,
+                             (const void*)paint_tiles<3, int32_t, true, true>,
+                             (const void*)paint_tiles<3, uint32_t, true, true>};
         for (const void* f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PAINT_DYN64);
     });
@@ -1208,20 +1557,23 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     int32_t* bb = boxes ? boxes : (int32_t*)(base + lay.bb);
     int32_t* maxd = (int32_t*)(base + lay.maxd);
     uint32_t* toff = (uint32_t*)(base + lay.toff);
+    uint32_t* toff_big = (uint32_t*)(base + lay.toff_big);
     uint32_t* counter = (uint32_t*)(base + lay.counter);
     uint32_t* zf = (uint32_t*)(base + lay.zf);
     int32_t* kd = (int32_t*)(base + lay.kd);
     uint32_t* spill = (uint32_t*)(base + lay.spill);
     int32_t* colmax = (int32_t*)(base + lay.colmax);
+    uint32_t* work = (uint32_t*)(base + lay.work);
+    uint32_t* bmap = (uint32_t*)(base + lay.bmap);
+    const SpillPool pool{(uint32_t*)(base + lay.pool), (unsigned long long*)(counter + 4), lay.pool_words};
     const size_t ncol = g.ndim == 3 ? (size_t)g.ny * g.nx : 0;
     const int chunk = ctx->tune.front_chunk > 0 ? ctx->tune.front_chunk : 64;
-    uint32_t* gmax = counter + 1;
     const uint32_t nlab = max_label + 1;
 
     {
         ProfScope _p(ctx, s, "init_label_arrays");
-        const size_t work = std::max((size_t)nlab, std::min(ncol, (size_t)1 << 20));
-        init_label_arrays<<<(unsigned)((work + 255) / 256), 256, 0, s>>>(boxes ? nullptr : bb, maxd, nlab, gmax,
+        const size_t items = std::max((size_t)nlab, std::min(ncol, (size_t)1 << 20));
+        init_label_arrays<<<(unsigned)((items + 255) / 256), 256, 0, s>>>(boxes ? nullptr : bb, maxd, nlab, counter,
                                                                           colmax, ncol);
     }
     if (!boxes) {
@@ -1235,7 +1587,7 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             const dim3 grid((g.nx + 63) / 64, (g.ny + PR_TY - 1) / PR_TY, (g.nz + PR_ZB - 1) / PR_ZB);
             if (w)
                 prune3d<L, true><<<grid, dim3(64, PR_TY), 0, s>>>(lab, D, g.nx, g.ny, g.nz, max_label, tabw, kd, lt,
-                                                                   maxd, colmax, ctx->d_err);
+                                                                   maxd, colmax, ctx->d_err, sp.wz, sp.wy, sp.wx);
             else
                 prune3d<L><<<grid, dim3(64, PR_TY), 0, s>>>(lab, D, g.nx, g.ny, g.nz, max_label, ctx->d_prune3, kd,
                                                              lt, maxd, colmax, ctx->d_err);
@@ -1245,23 +1597,40 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             const dim3 grid((g.nx + 63) / 64, g.ny, (g.nz + chunk - 1) / chunk);
             if (w)
                 fronts3d<true><<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill,
-                                                                      sp.wz);
+                                                                      work, counter + 2, lay.wcap, pool, bmap, sp.wz);
             else
-                fronts3d<<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill);
+                fronts3d<<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill,
+                                                                work, counter + 2, lay.wcap, pool, bmap);
+        }
+        {
+            // columns with more listed centres than the front pass holds (objects of
+            // large radius); returns at once when there are none
+            ProfScope _p(ctx, s, "fronts3d_long");
+            const int blocks = ctx->n_cu * 2;
+            if (w)
+                fronts3d_long<true><<<blocks, 256, fronts3d_long_lds(), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf,
+                                                                            work, counter + 2, lay.wcap, counter + 3,
+                                                                            pool, sp.wz);
+            else
+                fronts3d_long<<<blocks, 256, fronts3d_long_lds(), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, work,
+                                                                      counter + 2, lay.wcap, counter + 3, pool);
         }
     } else {
         ProfScope _p(ctx, s, "pixels2d");
         if (w)
             pixels2d<L, true><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(lab, D, g.nx, g.ny, max_label,
-                                                                                  tabw, zf, lt, maxd);
+                                                                                  tabw, zf, lt, maxd, sp.wy, sp.wx);
         else
             pixels2d<L><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(lab, D, g.nx, g.ny, max_label,
                                                                             ctx->d_prune2, zf, lt, maxd);
     }
     const int tile_y = paint_tile_rows(ctx);
+    // objects with balls reaching BAND_REACH or more along y or x (3D) take the banded
+    // launch: largest D above BAND_REACH^2 times the smaller in-plane squared spacing
+    const int band_d = g.ndim == 3 ? BAND_REACH * BAND_REACH * std::min(sp.wy, sp.wx) : INT_MAX;
     {
         ProfScope _p(ctx, s, "plan_tiles");
-        plan_tiles<<<1, 1024, 0, s>>>(bb, nlab, tile_y, toff, counter);
+        plan_tiles<<<1, 1024, 0, s>>>(bb, maxd, nlab, tile_y, band_d, toff, toff_big, counter);
     }
     // two blocks of 512 threads per CU (32-row tiles) when both fit in the LDS, else one
     // block of 1024 threads: two blocks overlap each other's slice barriers
@@ -1270,21 +1639,36 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     const int threads = two ? PAINT_THREADS / 2 : PAINT_THREADS;
     const size_t lds = paint_lds(tile_y, threads);
     const int blocks = ctx->n_cu * (two ? 2 : 1);
-    {
+    if (g.ndim == 3) {
+        {
+            // objects of large reach (returns at once when there are none)
+            ProfScope _p(ctx, s, "paint_tiles_banded");
+            if (w)
+                paint_tiles<3, L, true, true><<<blocks, threads, lds, s>>>(
+                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
+                    pool.base, bmap, chunk, ms, D, sp);
+            else
+                paint_tiles<3, L, false, true><<<blocks, threads, lds, s>>>(
+                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
+                    pool.base, bmap, chunk, ms, D);
+        }
         ProfScope _p(ctx, s, "paint_tiles");
-        if (g.ndim == 3 && w)
-            paint_tiles<3, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
-                                                                     g.nz, tile_y, counter, lt, spill, chunk, ms, D,
-                                                                     sp);
-        else if (g.ndim == 3)
-            paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny,
-                                                               g.nz, tile_y, counter, lt, spill, chunk, ms, D);
-        else if (w)
-            paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
-                                                                     tile_y, counter, lt, spill, chunk, ms, D, sp);
+        if (w)
+            paint_tiles<3, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
+                                                                 tile_y, counter, lt, spill, pool.base, bmap, chunk,
+                                                                 ms, D, sp);
         else
-            paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
-                                                               tile_y, counter, lt, spill, chunk, ms, D);
+            paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
+                                                           tile_y, counter, lt, spill, pool.base, bmap, chunk, ms, D);
+    } else {
+        ProfScope _p(ctx, s, "paint_tiles");
+        if (w)
+            paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
+                                                                 tile_y, counter, lt, spill, pool.base, bmap, chunk,
+                                                                 ms, D, sp);
+        else
+            paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1, tile_y,
+                                                           counter, lt, spill, pool.base, bmap, chunk, ms, D);
     }
     return hip_check(hipGetLastError(), "thickness launch");
 }

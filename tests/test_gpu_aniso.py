@@ -126,10 +126,15 @@ def _weighted_ball(weights, R):
 
 
 @pytest.mark.parametrize("weights,R", [((4, 1, 1), 3000), ((1, 4, 9), 2500), ((9, 1, 1), 12000),
-                                       ((4, 1), 40000), ((1, 16), 30000)])
+                                       ((4, 1), 40000), ((1, 16), 30000),
+                                       ((200, 180, 220), 60000), ((255, 250), 8000000),
+                                       ((1, 4, 4), 14000)])
 def test_large_weighted_balls(gpu, weights, R):
     """Weighted balls wide enough to span several paint tiles and to give long
-    z-fronts (rescans and spills): LT equals the centre's D everywhere."""
+    z-fronts (rescans and spills): LT equals the centre's D everywhere.  The last
+    two take squared radii past the prune tables (the containment bound decides),
+    the 2D one with 4 k (d - 1) beyond 32 bits; the (1, 4, 4) ball has z columns of
+    up to 237 voxels (the long-list pass)."""
     m, above = _weighted_ball(weights, R)
     lab = m.astype(np.int32)
     _note(f"aniso ball w={weights} R={R} shape={lab.shape}")

@@ -149,14 +149,16 @@ def test_large_disc_and_ball(gpu, ndim, r):
     assert got["sphericity"][1] == pytest.approx(want_s, rel=RTOL)
 
 
-def test_large_ellipsoid_sampled_lt(gpu):
-    """An ellipsoid with semi-axes 120 (x) x 70 (y) x 40 (z) (D up to ~1,600, source
-    rows of more than three 64-column chunks): D against scipy, LT at 400 sampled voxels
-    from its definition (largest D(c) over centres c whose open ball holds the
-    voxel)."""
-    m, off = synth.ellipsoid_mask((120.0, 70.0, 40.0), np.eye(3), (0.25, 0.5, 0.75))
+@pytest.mark.parametrize("axes", [(120.0, 70.0, 40.0), (50.0, 60.0, 170.0)])
+def test_large_ellipsoid_sampled_lt(gpu, axes):
+    """Ellipsoids with semi-axes 120 (x) x 70 (y) x 40 (z) (D up to ~1,600, source
+    rows of more than three 64-column chunks) and 50 x 60 x 170 (columns of up to 340
+    voxels: more listed centres than the front pass holds, so the long-list pass and
+    the spill pool take them): D against scipy, LT at 400 sampled voxels from its
+    definition (largest D(c) over centres c whose open ball holds the voxel)."""
+    m, off = synth.ellipsoid_mask(axes, np.eye(3), (0.25, 0.5, 0.75))
     lab = np.pad(m.astype(np.uint16), 2)
-    _note(f"large ellipsoid shape={lab.shape}")
+    _note(f"large ellipsoid axes={axes} shape={lab.shape}")
     got = _run_both(gpu, lab)
     D = _scipy_dsq(lab == 1)
     np.testing.assert_array_equal(got["dist_sq"], D)
@@ -174,3 +176,45 @@ def test_large_ellipsoid_sampled_lt(gpu):
         d2 = sum((gg - pp) ** 2 for gg, pp in zip(g, p))
         want = int(D[sub][d2 < D[sub]].max())
         assert got["lt_sq"][tuple(p)] == want, tuple(p)
+
+
+def _two_grains():
+    """Two noisy superellipsoids that touch (label 2 overwrites where they meet):
+    label 1 with largest D 1115 (balls reaching 33 voxels, so the banded paint launch
+    takes it), label 2 with 763 (the plain launch) -- both launches write one field."""
+    rng = synth.rng_for(7100)
+    a, _ = synth.superellipsoid_mask((46.0, 40.0, 34.0), 0.7, 0.9, np.eye(3), 3.0, rng)
+    b, _ = synth.superellipsoid_mask((42.0, 36.0, 30.0), 1.2, 0.6, synth.haar_rotation(rng), 3.0, rng)
+    shape = (max(a.shape[0], b.shape[0]) + 4, max(a.shape[1], b.shape[1]) + 4, a.shape[2] + b.shape[2] + 4)
+    lab = np.zeros(shape, np.uint16)
+    lab[2:2 + a.shape[0], 2:2 + a.shape[1], 2:2 + a.shape[2]][a] = 1
+    o = 2 + a.shape[2] - 6
+    lab[2:2 + b.shape[0], 2:2 + b.shape[1], o:o + b.shape[2]][b] = 2
+    return lab
+
+
+@pytest.mark.parametrize("weights", [None, (4, 1, 1)])
+def test_banded_paint_bit_exact(gpu, weights):
+    """Objects of large reach are painted in value bands with a tile floor: D, LT and
+    the per-object measures against the oracle, element by element."""
+    torch, lt = gpu
+    lab = _two_grains()
+    _note(f"two grains shape={lab.shape} weights={weights}")
+    D, LT, _ = O.fields(lab, threads=16, weights=weights)
+    assert int(D[lab == 1].max()) > 1024 * (1 if weights is None else min(weights[1:]))
+    if weights is None:
+        got = _run_both(gpu, lab)
+    else:
+        t = torch.from_numpy(lab).cuda()
+        got = _to_host(*lt.pipeline_aniso(t, 2, weights))
+        lt.default_context().sync_status()
+    np.testing.assert_array_equal(got["dist_sq"], D)
+    np.testing.assert_array_equal(got["lt_sq"], LT)
+    sums = O.object_sums(lab, LT, 2)
+    vs = 1.0 if weights is None else math.sqrt(float(np.prod(weights)))
+    ref = dict(sums)
+    ref.update(O.closed_forms(sums, 3, voxel_size=vs))
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        np.testing.assert_array_equal(got[k][:3], ref[k])
+    for k in FLOAT_KEYS:
+        np.testing.assert_allclose(got[k][1:3], ref[k][1:3], rtol=RTOL, atol=0, err_msg=k)
