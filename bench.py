@@ -444,6 +444,25 @@ def extensions_bench(ctx, lab, dist_sq, lt_sq, max_label: int, reps: int = 10) -
     rec["voxels_per_s"] = Na / (rec["ms"] * 1e-3)
     rec["pipeline_hbm_frac"] = round(36.0 * Na / (rec["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     del out_a, lab_a
+    # large objects (the banded paint launch): one digital ball of radius 150 (D up to
+    # 22,501) and one noisy superellipsoid grain with semi-axes 150 x 120 x 97.5, each
+    # alone in a 512^3 volume -- the large-radius end of the EDT searches and ball cover
+    from paper_2504_05808_amd import synth
+    rng = synth.rng_for(9150)
+    grain, _ = synth.superellipsoid_mask((150.0, 120.0, 97.5), 0.7, 0.9, synth.haar_rotation(rng), 3.0, rng)
+    for name, obj, what in (("pipeline_ball_r150", synth.ball_mask(150)[0], "one digital ball of radius 150"),
+                            ("pipeline_grain_150", grain,
+                             "one noisy superellipsoid grain, semi-axes 150 x 120 x 97.5 (Haar rotation)")):
+        big = np.zeros(tuple(lab.shape), np.uint16)
+        o = [(n - b) // 2 for n, b in zip(big.shape, obj.shape)]
+        big[o[0]:o[0] + obj.shape[0], o[1]:o[1] + obj.shape[1], o[2]:o[2] + obj.shape[2]] = obj
+        big_t = torch.from_numpy(big).to(lab.device)
+        out_b = (torch.empty_like(big_t, dtype=torch.int32), torch.empty_like(big_t, dtype=torch.int32),
+                 lt.alloc_measures(2, lab.device))
+        timed(name, lambda: lt.pipeline(big_t, 1, out=out_b, ctx=ctx), {})
+        out[name]["workload"] = f"{what} ({int(obj.sum())} voxels) in a 512^3 uint16 volume"
+        out[name]["voxels_per_s"] = float(obj.sum()) / (out[name]["ms"] * 1e-3)
+        del out_b, big_t, big
     # roughness-filtered roundness, half-width 2: three separable window passes
     # (x: labels, D, LT -> F; y: labels, F -> F; z: labels, F, D, LT -> per-label sums)
     timed("filtered_roundness_w2", lambda: lt.filtered_roundness(lab, dist_sq, lt_sq, max_label, 2, ctx=ctx),

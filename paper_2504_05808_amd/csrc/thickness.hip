@@ -383,8 +383,8 @@ static size_t fronts3d_lds(int chunk) {
 // appended.  Entries come four at a time (LDS broadcasts); four that no lane takes
 // cost one test.  dq[i] holds the D of entry
 // 4 i + 3; the wave stops once no lane has maxb below it.  Members go to p, newest first, or with
-// SPILL to out[0..k).  Returns the front length k; vtop gets the D of the first
-// member (the largest of the front).
+// SPILL to out[0..k).  Returns the front length k; with SPILL, vtop gets the D of
+// the first member (the largest of the front; without SPILL it is the oldest of p).
 // With W the residual is v - wz (z - zc)^2: A = v - wz zc^2, t = A + 2 wz z zc and the
 // threshold maxb + wz z^2 (full 32-bit products).
 template <bool SPILL, bool W = false>
@@ -417,7 +417,7 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
                         for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = app ? p[q - 1] : p[q];
                         p[0] = em ? w : p[0];
                     }
-                    vtop = (em && k == 0) ? v : vtop;
+                    if (SPILL) vtop = (em && k == 0) ? v : vtop;
                     k += app ? 1 : 0;
                     lastv = em ? v : lastv;
                     mz = em ? t[u] : mz;
@@ -503,6 +503,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     const uint32_t cap = (uint32_t)(SPILL_ROW_SLICE * chunk);
     uint32_t* region = spill + ((size_t)blockIdx.z * ny + y) * gridDim.x * (size_t)cap + (size_t)blockIdx.x * cap;
     const unsigned long long below = (1ull << lane) - 1ull;
+    int bacc0 = 0, bacc1 = 0;                         // the wave's group maxima of slices c0 + lane, + 64
     for (int cx = wid; cx < W; cx += 4) {
         const int cm = __builtin_amdgcn_readfirstlane(s_cm[cx]);
         uint32_t* out = tile + cx;                    // plane-0 words: out[(z - zs) * FZ_STRIDE]
@@ -541,10 +542,9 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
                 const uint32_t k = atomicAdd(nwork, 1u);
                 if (k < wcap) work[k] = ((uint32_t)blockIdx.z << 20) | (uint32_t)col;
             }
-            for (int z = c0 + lane; z < c1; z += 64) {
-                out[(z - zs) * FZ_STRIDE] = 7u << ZF_N_SHIFT;
-                atomicMax(&s_bm[z - c0], cm);         // bound for the long-list pass's fronts
-            }
+            for (int z = c0 + lane; z < c1; z += 64) out[(z - zs) * FZ_STRIDE] = 7u << ZF_N_SHIFT;
+            bacc0 = max(bacc0, cm);                   // bound for the long-list pass's fronts
+            bacc1 = max(bacc1, cm);
             continue;
         }
         if (lane < 4) list[cnt + lane] = 0u;          // padding: keys 0 count for no entry
@@ -600,26 +600,36 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             uint32_t p[ZF_PLANES];
 #pragma unroll
             for (int q = 0; q < ZF_PLANES; ++q) p[q] = 0u;
-            int m = 0, vtop = 0, vdummy = 0;
+            int m = 0, vtop = 0;
             uint32_t at = 0;
             int where = 0;                            // long front: 1 block region, 2 pool, 0 rescan
             if (__ballot(live)) {
                 m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, vtop, wz);
-                if (m > ZF_PLANES) {
-                    at = atomicAdd(&s_used, (uint32_t)m);
-                    where = at + (uint32_t)m <= cap ? 1 : 0;
+                // the front's largest D: its first member, the oldest in p (a longer
+                // front's comes from the spill scan)
+                const uint32_t first = m == 1 ? p[0] : m == 2 ? p[1] : m == 3 ? p[2] : p[3];
+                vtop = (int)(first & ZF_D_MASK);
+                if (__ballot(m > ZF_PLANES)) {        // long fronts in the wave
+                    if (m > ZF_PLANES) {
+                        at = atomicAdd(&s_used, (uint32_t)m);
+                        where = at + (uint32_t)m <= cap ? 1 : 0;
+                    }
+                    pool_take(pool, m > ZF_PLANES && where == 0, m, lane, at, where);
+                    const bool again = where != 0;    // second scan: the whole front to the spill
+                    if (__ballot(again))
+                        front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p,
+                                             (where == 2 ? pool.base : region) + at, vtop, wz);
+                    // a rescanned column may paint any of its kept centres
+                    if (m > ZF_PLANES && where == 0) vtop = cm;
                 }
-                pool_take(pool, m > ZF_PLANES && where == 0, m, lane, at, where);
-                const bool again = where != 0;        // second scan: the whole front to the spill
-                if (__ballot(again))
-                    front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p,
-                                         (where == 2 ? pool.base : region) + at, vdummy, wz);
+            }
+            if (m > 0) {                              // group maximum of this slice, per wave
+                if (zr == c0) bacc0 = max(bacc0, vtop);
+                else bacc1 = max(bacc1, vtop);
             }
             if (z < c1) {
                 uint32_t w0;
                 const size_t i = (size_t)z * plane + col;
-                // a rescanned column may paint any of its kept centres: bound by the column's largest
-                if (m > 0) atomicMax(&s_bm[z - c0], m > ZF_PLANES && where == 0 ? cm : vtop);
                 if (m > ZF_PLANES) {
                     w0 = long_front_word(m, at, where);
                     if (where == 2) zf[n + i] = at;
@@ -633,6 +643,8 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             }
         }
     }
+    if (c0 + lane < c1) atomicMax(&s_bm[lane], bacc0);
+    if (c0 + 64 + lane < c1) atomicMax(&s_bm[64 + lane], bacc1);
     __syncthreads();
     for (int q = wid; q < c1 - c0; q += 4)
         if (lane < W) zf[(size_t)(c0 + q) * plane + rowi + lane] = tile[q * FZ_STRIDE + lane];
@@ -665,6 +677,7 @@ fronts3d_long(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     const size_t plane = (size_t)ny * nx;
     const size_t n = plane * nz;
     const uint32_t total = min(*nwork, wcap);        // final: the front pass has ended
+    if (total == 0u) return;
     const unsigned long long below = (1ull << lane) - 1ull;
     for (;;) {
         uint32_t it = 0u;
@@ -1075,6 +1088,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     const int lane = tid & 63, wid = tid >> 6;
     const int nwaves = blockDim.x >> 6;
     const uint32_t total = toff[nlab];
+    if (total == 0u) return;                       // no item for this launch
     const size_t n = (size_t)nx * ny * nz;
     const int ngroups = (nx + 63) / 64;
     // The table is all zero between slices: every cell a slice uses is cleared by
