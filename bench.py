@@ -397,7 +397,7 @@ def mlp_bench(args):
     net.close()
 
 
-def extensions_bench(ctx, lab, dist_sq, lt_sq, max_label: int, reps: int = 10) -> dict:
+def extensions_bench(ctx, lab, dist_sq, lt_sq, max_label: int, reps: int = 10, large: bool = True) -> dict:
     """The calls beyond the step, each timed alone on the resident volume (outside
     the step's timed region): kernel times from the library's per-launch HIP events
     and algorithmic GB/s against the HBM peak."""
@@ -448,11 +448,14 @@ def extensions_bench(ctx, lab, dist_sq, lt_sq, max_label: int, reps: int = 10) -
     # 22,501) and one noisy superellipsoid grain with semi-axes 150 x 120 x 97.5, each
     # alone in a 512^3 volume -- the large-radius end of the EDT searches and ball cover
     from paper_2504_05808_amd import synth
-    rng = synth.rng_for(9150)
-    grain, _ = synth.superellipsoid_mask((150.0, 120.0, 97.5), 0.7, 0.9, synth.haar_rotation(rng), 3.0, rng)
-    for name, obj, what in (("pipeline_ball_r150", synth.ball_mask(150)[0], "one digital ball of radius 150"),
-                            ("pipeline_grain_150", grain,
-                             "one noisy superellipsoid grain, semi-axes 150 x 120 x 97.5 (Haar rotation)")):
+    large_objects = ()
+    if large:
+        rng = synth.rng_for(9150)
+        grain, _ = synth.superellipsoid_mask((150.0, 120.0, 97.5), 0.7, 0.9, synth.haar_rotation(rng), 3.0, rng)
+        large_objects = (("pipeline_ball_r150", synth.ball_mask(150)[0], "one digital ball of radius 150"),
+                         ("pipeline_grain_150", grain,
+                          "one noisy superellipsoid grain, semi-axes 150 x 120 x 97.5 (Haar rotation)"))
+    for name, obj, what in large_objects:
         big = np.zeros(tuple(lab.shape), np.uint16)
         o = [(n - b) // 2 for n, b in zip(big.shape, obj.shape)]
         big[o[0]:o[0] + obj.shape[0], o[1]:o[1] + obj.shape[1], o[2]:o[2] + obj.shape[2]] = obj
@@ -489,6 +492,9 @@ def main():
     ap.add_argument("--paint-rows", type=int, default=0, help="paint tile rows (32 or 64; 0 = default)")
     ap.add_argument("--paint-per-cu", type=int, default=0, help="paint blocks per CU (1 or 2; 0 = default)")
     ap.add_argument("--front-chunk", type=int, default=0, help="z-front chunk (32, 64, 128; 0 = default)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="leave out the large-object calls (profiled runs: their empty launches of the "
+                         "plain paint kernel would enter its per-dispatch averages)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for the HBM counters)")
     args = ap.parse_args()
@@ -609,7 +615,7 @@ def main():
     pipe_bytes = 36.0 * N
     pipe_gbs = pipe_bytes / (ms * 1e-3) / 1e9
 
-    ext = extensions_bench(ctx, lab, d, t, max_label)
+    ext = extensions_bench(ctx, lab, d, t, max_label, large=not args.no_large)
 
     cpu = None
     if not args.no_cpu_baseline:

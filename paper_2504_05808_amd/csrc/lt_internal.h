@@ -50,9 +50,9 @@ constexpr int ZF_PLANES = 4;
 constexpr uint32_t ZF_SPILL = 1u << 28;
 constexpr uint32_t ZF_POOL = 1u << 24;
 constexpr int ZF_LONG_MAX = 255;               // longest front the 8-bit length holds
-// Spill words per (row of 64 columns, slice) of the front pass: half a word per
-// voxel; a block whose long fronts need more takes them from the shared pool.
-constexpr int SPILL_ROW_SLICE = 32;
+// Spill words per (row of 64 columns, slice) of the front pass: one word per voxel;
+// a block whose long fronts need more takes them from the shared pool.
+constexpr int SPILL_ROW_SLICE = 64;
 
 // Shared spill pool of the front passes (one word per voxel): long fronts that do
 // not fit their block's region.  `used` counts requested words (64-bit: requests go

@@ -383,13 +383,12 @@ static size_t fronts3d_lds(int chunk) {
 // appended.  Entries come four at a time (LDS broadcasts); four that no lane takes
 // cost one test.  dq[i] holds the D of entry
 // 4 i + 3; the wave stops once no lane has maxb below it.  Members go to p, newest first, or with
-// SPILL to out[0..k).  Returns the front length k; with SPILL, vtop gets the D of
-// the first member (the largest of the front; without SPILL it is the oldest of p).
+// SPILL to out[0..k).  Returns the front length k.
 // With W the residual is v - wz (z - zc)^2: A = v - wz zc^2, t = A + 2 wz z zc and the
 // threshold maxb + wz z^2 (full 32-bit products).
 template <bool SPILL, bool W = false>
 __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int cnt4, int z, bool act,
-                                          uint32_t (&p)[ZF_PLANES], uint32_t* out, int& vtop, int wz = 1) {
+                                          uint32_t (&p)[ZF_PLANES], uint32_t* out, int wz = 1) {
     const int z2 = W ? 2 * wz * z : 2 * z, zsq = W ? wz * z * z : __mul24(z, z);
     int mz = act ? zsq : INT_MAX;
     int k = 0, lastv = 0;                 // front length, D of the last member
@@ -417,7 +416,6 @@ __device__ __forceinline__ int front_scan(const uint4* ent, const int* dq, int c
                         for (int q = ZF_PLANES - 1; q >= 1; --q) p[q] = app ? p[q - 1] : p[q];
                         p[0] = em ? w : p[0];
                     }
-                    if (SPILL) vtop = (em && k == 0) ? v : vtop;
                     k += app ? 1 : 0;
                     lastv = em ? v : lastv;
                     mz = em ? t[u] : mz;
@@ -480,7 +478,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          uint32_t* __restrict__ bmap, int wz = 1) {
     extern __shared__ __align__(16) uint32_t S[];
     __shared__ int s_cm[64];
-    __shared__ int s_bm[128];                         // per slice: largest D of the block's fronts
+    __shared__ int s_bm[128];                         // per slice: bound on the block's front values
     __shared__ uint32_t s_used;                       // words of the block's spill region in use
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);    // wave-uniform, in a scalar register
@@ -503,7 +501,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     const uint32_t cap = (uint32_t)(SPILL_ROW_SLICE * chunk);
     uint32_t* region = spill + ((size_t)blockIdx.z * ny + y) * gridDim.x * (size_t)cap + (size_t)blockIdx.x * cap;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int bacc0 = 0, bacc1 = 0;                         // the wave's group maxima of slices c0 + lane, + 64
+    int bacc0 = 0, bacc1 = 0;                         // the wave's group bounds of slices c0 + lane, + 64
     for (int cx = wid; cx < W; cx += 4) {
         const int cm = __builtin_amdgcn_readfirstlane(s_cm[cx]);
         uint32_t* out = tile + cx;                    // plane-0 words: out[(z - zs) * FZ_STRIDE]
@@ -600,15 +598,11 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             uint32_t p[ZF_PLANES];
 #pragma unroll
             for (int q = 0; q < ZF_PLANES; ++q) p[q] = 0u;
-            int m = 0, vtop = 0;
+            int m = 0;
             uint32_t at = 0;
             int where = 0;                            // long front: 1 block region, 2 pool, 0 rescan
             if (__ballot(live)) {
-                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, vtop, wz);
-                // the front's largest D: its first member, the oldest in p (a longer
-                // front's comes from the spill scan)
-                const uint32_t first = m == 1 ? p[0] : m == 2 ? p[1] : m == 3 ? p[2] : p[3];
-                vtop = (int)(first & ZF_D_MASK);
+                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, wz);
                 if (__ballot(m > ZF_PLANES)) {        // long fronts in the wave
                     if (m > ZF_PLANES) {
                         at = atomicAdd(&s_used, (uint32_t)m);
@@ -618,14 +612,14 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
                     const bool again = where != 0;    // second scan: the whole front to the spill
                     if (__ballot(again))
                         front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p,
-                                             (where == 2 ? pool.base : region) + at, vtop, wz);
-                    // a rescanned column may paint any of its kept centres
-                    if (m > ZF_PLANES && where == 0) vtop = cm;
+                                             (where == 2 ? pool.base : region) + at, wz);
                 }
             }
-            if (m > 0) {                              // group maximum of this slice, per wave
-                if (zr == c0) bacc0 = max(bacc0, vtop);
-                else bacc1 = max(bacc1, vtop);
+            // group bound of this slice: the column's largest kept D (every disc it adds,
+            // front or rescan, has no larger value)
+            if (m > 0) {
+                if (zr == c0) bacc0 = max(bacc0, cm);
+                else bacc1 = max(bacc1, cm);
             }
             if (z < c1) {
                 uint32_t w0;
@@ -758,12 +752,11 @@ fronts3d_long(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             uint32_t at = 0;
             int where = 0;
             if (__ballot(live)) {
-                int vd = 0;                           // the group bound is the column's largest D
-                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, vd, wz);
+                m = front_scan<false, WG>((const uint4*)ent, dq, cnt4, z, live, p, nullptr, wz);
                 pool_take(pool, m > ZF_PLANES && m <= ZF_LONG_MAX, m, lane, at, where);
                 const bool again = where != 0;
                 if (__ballot(again))
-                    front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p, pool.base + at, vd, wz);
+                    front_scan<true, WG>((const uint4*)ent, dq, cnt4, z, again, p, pool.base + at, wz);
             }
             if (z < c1) {
                 const size_t i = (size_t)z * plane + col;
@@ -1298,15 +1291,15 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             };
             if constexpr (BAND) {
                 // Objects of large reach: the source groups (one source row x 64 columns)
-                // in three bands of their largest front value -- those holding the
-                // object's largest D, those of at least half of it, the rest -- with the
-                // tile's floor (smallest value painted so far over the object's cells in
-                // this slice) taken after the first two.  A group whose largest value
-                // does not exceed the floor, and any disc that does not, cannot raise a
-                // cell and is skipped.
+                // in three bands of their bound on the front values (the front pass's
+                // group bounds) -- those reaching the object's largest D, those of at
+                // least half of it, the rest -- with the tile's floor (smallest value
+                // painted so far over the object's cells in this slice) taken after the
+                // first two.  A group whose bound does not exceed the floor, and any disc
+                // whose value does not, cannot raise a cell and is skipped.
                 const uint32_t* bms = bmap + (size_t)pz * ny * ngroups;
                 int fl = 0;
-                // group maxima of a source row, loaded together BM_CH chunks of 64
+                // group bounds of a source row, loaded together BM_CH chunks of 64
                 // columns at a time (one round trip for rows up to 384 columns)
                 constexpr int BM_CH = 6;
                 const int nch = (sx1 - sx0 + 63) >> 6;
@@ -1507,7 +1500,8 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.work = at;    at += align256((size_t)o.wcap * sizeof(uint32_t));
     o.pool_words = g.ndim == 3 ? g.n : 0;
     o.pool = at;    at += align256(o.pool_words * sizeof(uint32_t));
-    // largest front value per (slice, row, 64-column group)
+    // bound on the front values per (slice, row, 64-column group): the largest kept D
+    // of the group's columns that have a front in the slice
     o.bmap = at;    at += g.ndim == 3 ? align256((size_t)g.nz * g.ny * ((g.nx + 63) / 64) * sizeof(uint32_t)) : 0;
     o.total = at;
     return o;
