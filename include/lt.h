@@ -148,7 +148,7 @@ lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
  * synchronise.  The caller still allocates every input and output.
  *   - a problem whose scratch (lt_pipeline_static_bytes) exceeds the fixed array
  *     returns LT_E_WORKSPACE before anything is launched; e.g. a 128^3 volume with
- *     a few hundred labels needs about 50 MiB;
+ *     a few hundred labels needs about 57 MiB;
  *   - all calls on one device share that device's array, and each call leaves its
  *     contents behind (every kernel initialises what it reads), so calls that
  *     overlap in time on one device -- on different streams or contexts, or from

@@ -1489,10 +1489,10 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.counter = at; at += 256;
     o.zf = at;      at += align256((g.ndim == 3 ? ZF_PLANES : 1) * g.n * sizeof(uint32_t));
     o.kd = at;      at += g.ndim == 3 ? align256(g.n * sizeof(int32_t)) : 0;
-    // spill regions of the front pass: one per (row of 64 columns, z chunk), sized
-    // for the largest chunk (the z extent rounded up by at most 127 slices)
+    // spill regions of the front pass: one per (row of 64 columns, z chunk); the chunks
+    // (32, 64 or 128 slices) all divide 128, so the z extent rounded up to 128 holds them
     o.spill = at;
-    at += g.ndim == 3 ? align256((size_t)((g.nx + 63) / 64) * g.ny * (g.nz + 127) * SPILL_ROW_SLICE *
+    at += g.ndim == 3 ? align256((size_t)((g.nx + 63) / 64) * g.ny * ((g.nz + 127) & ~127) * SPILL_ROW_SLICE *
                                  sizeof(uint32_t))
                       : 0;
     o.colmax = at;  at += g.ndim == 3 ? align256((size_t)g.ny * g.nx * sizeof(int32_t)) : 0;
