@@ -1277,13 +1277,21 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             // labels and plane-0 fronts of a whole source row, loaded together; the
             // next row of the wave is fetched while the current one is processed
             constexpr int MAXC = 3;                       // source rows span <= 64 + 2 * 64 columns
+            // Source rows of at most 32 columns (3D, small objects): two rows per wave
+            // iteration, 32 lanes each (3D disc entries carry their own source row).  Four
+            // rows of 16 lanes for rows of at most 16 columns measured slower.
+            const int rs = NDIM == 3 && sx1 - sx0 <= 32 ? 1 : 0;
+            const int lx = lane & ((64 >> rs) - 1);       // the lane's column in its row chunk
+            const int lrow = lane >> (6 - rs);            // the lane's row within the iteration
+            const int rfirst = sy0 + (wid << rs), rstep = nwaves << rs;
             L nlv[MAXC];
             uint32_t nev[MAXC];
-            auto fetch_row = [&](int syn) {
+            auto fetch_row = [&](int sbn) {
+                const int syn = sbn + lrow;
                 const size_t ri = ((size_t)pz * ny + syn) * nx;
 #pragma unroll
                 for (int c = 0; c < MAXC; ++c) {
-                    const int sx = sx0 + c * 64 + lane;
+                    const int sx = sx0 + c * 64 + lx;
                     const bool in = syn < sy1 && sx < sx1;
                     nlv[c] = in ? lab[ri + sx] : L(0);
                     nev[c] = in ? zf[ri + sx] : 0u;
@@ -1339,9 +1347,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     if (band < 2) fl = tile_floor(band, pz);
                 }
             } else {
-                fetch_row(sy0 + wid);
-                for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
-                    sylast = sy;
+                fetch_row(rfirst);
+                for (int sb = rfirst; sb < sy1; sb += rstep) {
+                    const int sy = sb + lrow;                 // this lane's source row (past sy1: no column)
+                    sylast = sb;
                     L lv[MAXC];
                     uint32_t ev[MAXC];
 #pragma unroll
@@ -1349,14 +1358,14 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                         lv[c] = nlv[c];
                         ev[c] = nev[c];
                     }
-                    fetch_row(sy + nwaves);
+                    fetch_row(sb + rstep);
                     const size_t rowi = ((size_t)pz * ny + sy) * nx;
                     // a disc of residual b reaches a tile cell only if b exceeds the squared
                     // distance from its centre to the tile: discs below it are not listed
                     const int ddy = max(max(t.ty0 - sy, sy - (t.ty0 + t.H - 1)), 0);
                     const int rowd = W ? spc.wy * ddy * ddy : ddy * ddy;
                     for (int c = 0; c * 64 < sx1 - sx0; ++c) {
-                        const int sx = sx0 + c * 64 + lane;
+                        const int sx = sx0 + c * 64 + lx;
                         const int ddx = max(max(t.tx0 - sx, sx - (t.tx0 + t.W - 1)), 0);
                         const int need = rowd + (W ? spc.wx * ddx * ddx : ddx * ddx);
                         L lc;
