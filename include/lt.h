@@ -33,6 +33,12 @@
  *     no-op returning LT_OK.
  *   - calls on one context must not overlap in time (they share its scratch
  *     memory); use one context per concurrent stream.
+ *   - environment: LT_LOG=1 prints one line on stderr for every error status
+ *     (the call it came from, the status and its message), LT_LOG=2 also one line
+ *     per call that takes a volume (name, shape, label type, label bound);
+ *     LT_FAULT_INJECT=alloc makes every device allocation of the library fail
+ *     with LT_E_ALLOC, alloc:N after N more successes (tests of the failure
+ *     paths).  Both are read at every use.
  */
 #ifndef LT_H
 #define LT_H

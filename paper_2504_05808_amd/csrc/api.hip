@@ -16,12 +16,44 @@
 namespace lt {
 
 static thread_local char g_err[512] = "";
+static thread_local const char* g_call = nullptr;    // the exported call running on this thread
+
+// LT_LOG (environment): unset or 0, silent; 1, one line on stderr per error status (the
+// call it came from, the status and its message); 2, also one line per exported call
+// that takes a volume (its name, shape, label type and label bound).  Read at every
+// use (host work only), so a process may change it between calls.
+static int log_level() {
+    const char* e = getenv("LT_LOG");
+    return e ? atoi(e) : 0;
+}
+
+CallScope::CallScope(const char* fn, int ndim, const int64_t* shape, int dtype, long long max_label)
+    : prev(g_call) {
+    g_call = fn;
+    if ((!shape && dtype < 0) || log_level() < 2) return;
+    char buf[256];
+    int k = snprintf(buf, sizeof(buf), "[lt] %s", fn);
+    if (shape && ndim >= 1 && ndim <= 3) {
+        k += snprintf(buf + k, sizeof(buf) - k, " shape=");
+        for (int i = 0; i < ndim && k < (int)sizeof(buf); ++i)
+            k += snprintf(buf + k, sizeof(buf) - k, i ? "x%lld" : "%lld", (long long)shape[i]);
+    }
+    static const char* const names[] = {"u16", "i32", "u32"};    // LT_U16, LT_I32, LT_U32
+    if (dtype >= 0 && k < (int)sizeof(buf))
+        k += dtype >= LT_U16 && dtype <= LT_U32 ? snprintf(buf + k, sizeof(buf) - k, " dtype=%s", names[dtype - 1])
+                                                : snprintf(buf + k, sizeof(buf) - k, " dtype=%d", dtype);
+    if (max_label >= 0 && k < (int)sizeof(buf)) snprintf(buf + k, sizeof(buf) - k, " max_label=%lld", max_label);
+    fprintf(stderr, "%s\n", buf);
+}
+
+CallScope::~CallScope() { g_call = prev; }
 
 lt_status set_error(lt_status s, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+    if (log_level() >= 1) fprintf(stderr, "[lt] %s: %s: %s\n", g_call ? g_call : "liblt", lt_status_str(s), g_err);
     return s;
 }
 
@@ -314,6 +346,7 @@ const char* lt_status_str(lt_status s) {
 }
 
 lt_status lt_ctx_create(lt_ctx** out, int device) {
+    lt::CallScope call_scope_("lt_ctx_create");
     if (!out) return set_error(LT_E_ARG, "out is NULL");
     *out = nullptr;
     // a context needs device memory: with allocations failing by injection it fails
@@ -357,6 +390,7 @@ lt_status lt_ctx_create(lt_ctx** out, int device) {
 }
 
 lt_status lt_ctx_destroy(lt_ctx* ctx) {
+    lt::CallScope call_scope_("lt_ctx_destroy");
     if (!ctx) return LT_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
@@ -382,6 +416,7 @@ static lt_status common_checks(lt_ctx* ctx, const void* labels, lt_dtype dtype, 
 
 lt_status lt_edt(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                  int32_t* dist_sq, void* stream) {
+    lt::CallScope call_scope_("lt_edt", ndim, shape, (int)dtype, -1);
     Geom g;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
     if (st) return st;
@@ -394,6 +429,7 @@ lt_status lt_edt(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, cons
 lt_status lt_thickness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
                        const int64_t* shape, const int32_t* dist_sq, uint32_t max_label,
                        int32_t* lt_sq, void* stream) {
+    lt::CallScope call_scope_("lt_thickness", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
     if (st) return st;
@@ -408,6 +444,7 @@ lt_status lt_thickness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim
 lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
                              const int64_t* shape, const int32_t* lt_sq, uint32_t max_label,
                              const lt_measures* out, void* stream) {
+    lt::CallScope call_scope_("lt_object_measures", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
     if (st) return st;
@@ -424,6 +461,7 @@ lt_status lt_object_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, in
 lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                       uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
                       void* stream) {
+    lt::CallScope call_scope_("lt_pipeline", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
     if (st) return st;
@@ -439,6 +477,7 @@ lt_status lt_pipeline(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
 
 lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                            uint32_t max_label, uint64_t* volume, float* area, float* sphericity, void* stream) {
+    lt::CallScope call_scope_("lt_mesh_measures", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
     if (st) return st;
@@ -451,6 +490,7 @@ lt_status lt_mesh_measures(lt_ctx* ctx, const void* labels, lt_dtype dtype, int 
 
 lt_status lt_edt_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                        const int32_t* sq_spacing, int32_t* dist_sq, void* stream) {
+    lt::CallScope call_scope_("lt_edt_aniso", ndim, shape, (int)dtype, -1);
     Geom g;
     Spacing sp;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
@@ -464,6 +504,7 @@ lt_status lt_edt_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim
 lt_status lt_thickness_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                              const int32_t* sq_spacing, const int32_t* dist_sq, uint32_t max_label, int32_t* lt_sq,
                              void* stream) {
+    lt::CallScope call_scope_("lt_thickness_aniso", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     Spacing sp;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
@@ -479,6 +520,7 @@ lt_status lt_thickness_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, in
 lt_status lt_object_measures_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                                    const int32_t* sq_spacing, const int32_t* lt_sq, uint32_t max_label,
                                    const lt_measures* out, void* stream) {
+    lt::CallScope call_scope_("lt_object_measures_aniso", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     Spacing sp;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
@@ -496,6 +538,7 @@ lt_status lt_object_measures_aniso(lt_ctx* ctx, const void* labels, lt_dtype dty
 lt_status lt_pipeline_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                             const int32_t* sq_spacing, uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq,
                             const lt_measures* out, void* stream) {
+    lt::CallScope call_scope_("lt_pipeline_aniso", ndim, shape, (int)dtype, (long long)max_label);
     Geom g;
     Spacing sp;
     lt_status st = common_checks(ctx, labels, dtype, ndim, shape, &g);
@@ -513,6 +556,7 @@ lt_status lt_pipeline_aniso(lt_ctx* ctx, const void* labels, lt_dtype dtype, int
 lt_status lt_filtered_roundness(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                                 const int32_t* dist_sq, const int32_t* lt_sq, uint32_t max_label, int half_width,
                                 float* roundness, void* stream) {
+    lt::CallScope call_scope_("lt_filtered_roundness", ndim, shape, (int)dtype, (long long)max_label);
     if (half_width < 0 || half_width > LT_ROUGH_MAX_HALF_WIDTH)
         return set_error(LT_E_ARG, "half_width %d outside 0..%d", half_width, LT_ROUGH_MAX_HALF_WIDTH);
     if (max_label > (1u << 28)) return set_error(LT_E_ARG, "max_label %u exceeds 2^28", max_label);
@@ -528,6 +572,7 @@ lt_status lt_filtered_roundness(lt_ctx* ctx, const void* labels, lt_dtype dtype,
 
 lt_status lt_remap_roundness(lt_ctx* ctx, const float* roundness, uint32_t n, float r_min, float* out,
                              void* stream) {
+    lt::CallScope call_scope_("lt_remap_roundness");
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     if (n == 0) return LT_OK;
     if (!roundness || !out) return set_error(LT_E_ARG, "roundness or out is NULL");
@@ -539,6 +584,7 @@ lt_status lt_remap_roundness(lt_ctx* ctx, const float* roundness, uint32_t n, fl
 }
 
 lt_status lt_mesh_table(int ndim, double* out) {
+    lt::CallScope call_scope_("lt_mesh_table");
     if (ndim != 2 && ndim != 3) return set_error(LT_E_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
     if (!out) return set_error(LT_E_ARG, "out is NULL");
     return mesh_table_host(ndim, out);
@@ -553,6 +599,7 @@ size_t lt_pipeline_static_bytes(int ndim, const int64_t* shape, uint32_t max_lab
 lt_status lt_pipeline_static(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                              uint32_t max_label, int32_t* dist_sq, int32_t* lt_sq, const lt_measures* out,
                              void* stream) {
+    lt::CallScope call_scope_("lt_pipeline_static", ndim, shape, (int)dtype, (long long)max_label);
     // sizes first (host arithmetic only), then the common checks, which select the device
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     Geom g;
@@ -583,6 +630,7 @@ lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
                           const uint64_t* shell_sum_q23, uint32_t n, int ndim, float* mean_lt,
                           float* shell_mean_lt, float* sphericity, float* roundness,
                           void* stream) {
+    lt::CallScope call_scope_("lt_closed_forms");
     if (ndim != 2 && ndim != 3) return set_error(LT_E_SHAPE, "ndim must be 2 or 3 (got %d)", ndim);
     if (n == 0) return LT_OK;
     if (!volume || !sum_lt_q23 || !max_lt_sq || !shell_count || !shell_sum_q23 || !mean_lt ||
@@ -593,6 +641,7 @@ lt_status lt_closed_forms(const uint64_t* volume, const uint64_t* sum_lt_q23,
 }
 
 lt_status lt_ctx_info(lt_ctx* ctx, int* n_cu, uint64_t* lds_per_block, int* paint_tile_rows_out) {
+    lt::CallScope call_scope_("lt_ctx_info");
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     if (n_cu) *n_cu = ctx->n_cu;
     if (lds_per_block) *lds_per_block = ctx->lds_per_block;
@@ -601,12 +650,14 @@ lt_status lt_ctx_info(lt_ctx* ctx, int* n_cu, uint64_t* lds_per_block, int* pain
 }
 
 lt_status lt_profile_enable(lt_ctx* ctx, int on) {
+    lt::CallScope call_scope_("lt_profile_enable");
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     ctx->profile = on != 0;
     return LT_OK;
 }
 
 lt_status lt_profile_read(lt_ctx* ctx, lt_kernel_time* out, int cap, int* n_out) {
+    lt::CallScope call_scope_("lt_profile_read");
     if (!ctx || (cap > 0 && !out)) return set_error(LT_E_ARG, "ctx or out is NULL");
     lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
     if (st) return st;
@@ -643,6 +694,7 @@ lt_status lt_profile_read(lt_ctx* ctx, lt_kernel_time* out, int cap, int* n_out)
 }
 
 lt_status lt_profile_reset(lt_ctx* ctx) {
+    lt::CallScope call_scope_("lt_profile_reset");
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     int n = 0;
     lt_status st = lt_profile_read(ctx, nullptr, 0, &n);
@@ -651,6 +703,7 @@ lt_status lt_profile_reset(lt_ctx* ctx) {
 }
 
 lt_status lt_sync_status(lt_ctx* ctx, void* stream) {
+    lt::CallScope call_scope_("lt_sync_status");
     if (!ctx) return set_error(LT_E_ARG, "ctx is NULL");
     lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
     if (st) return st;

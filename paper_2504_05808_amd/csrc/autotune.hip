@@ -106,6 +106,7 @@ extern "C" {
 
 lt_status lt_autotune(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim, const int64_t* shape,
                       uint32_t max_label, const char* cache_path, int repeats, lt_tuning* best) {
+    lt::CallScope call_scope_("lt_autotune", ndim, shape, (int)dtype, (long long)max_label);
     if (!ctx || !labels) return set_error(LT_E_ARG, "ctx or labels is NULL");
     Geom g;
     lt_status st = geom_from(ndim, shape, &g);
@@ -183,6 +184,7 @@ lt_status lt_autotune(lt_ctx* ctx, const void* labels, lt_dtype dtype, int ndim,
 
 lt_status lt_autotune_batch(lt_ctx* ctx, const lt_volume* vols, int n, lt_dtype dtype,
                             const char* cache_path, int repeats, lt_tuning* best) {
+    lt::CallScope call_scope_("lt_autotune_batch", 0, nullptr, (int)dtype);
     if (!ctx || !vols || n <= 0) return set_error(LT_E_ARG, "ctx or vols is NULL / empty");
     double voxels = 0;
     int ndim = vols[0].ndim;

@@ -56,6 +56,7 @@ using namespace lt;
 extern "C" {
 
 lt_status lt_get_tuning(lt_ctx* ctx, lt_tuning* out) {
+    lt::CallScope call_scope_("lt_get_tuning");
     if (!ctx || !out) return set_error(LT_E_ARG, "ctx or out is NULL");
     out->paint_tile_rows = paint_tile_rows(ctx);
     out->paint_blocks_per_cu = ctx->tune.paint_blocks_per_cu;
@@ -65,6 +66,7 @@ lt_status lt_get_tuning(lt_ctx* ctx, lt_tuning* out) {
 }
 
 lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* t) {
+    lt::CallScope call_scope_("lt_set_tuning");
     if (!ctx || !t) return set_error(LT_E_ARG, "ctx or tuning is NULL");
     if (t->paint_tile_rows != 0 && t->paint_tile_rows != 32 && t->paint_tile_rows != 64)
         return set_error(LT_E_ARG, "paint_tile_rows must be 0, 32 or 64");
@@ -81,6 +83,7 @@ lt_status lt_set_tuning(lt_ctx* ctx, const lt_tuning* t) {
 }
 
 lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n, lt_dtype dtype, lt_batch** out) {
+    lt::CallScope call_scope_("lt_batch_create", 0, nullptr, (int)dtype);
     if (!ctx || !out || (n > 0 && !vols)) return set_error(LT_E_ARG, "ctx, vols or out is NULL");
     *out = nullptr;
     if (n < 0) return set_error(LT_E_ARG, "negative volume count");
@@ -186,6 +189,7 @@ lt_status lt_batch_create(lt_ctx* ctx, const lt_volume* vols, int n, lt_dtype dt
 }
 
 lt_status lt_batch_run(lt_batch* b, void* stream) {
+    lt::CallScope call_scope_("lt_batch_run");
     if (!b) return set_error(LT_E_ARG, "batch is NULL");
     lt_status st = hip_check(hipSetDevice(b->ctx->device), "hipSetDevice");
     if (st) return st;
@@ -194,6 +198,7 @@ lt_status lt_batch_run(lt_batch* b, void* stream) {
 }
 
 lt_status lt_batch_status(lt_batch* b, void* stream, int32_t* status) {
+    lt::CallScope call_scope_("lt_batch_status");
     if (!b) return set_error(LT_E_ARG, "batch is NULL");
     lt_status st = hip_check(hipSetDevice(b->ctx->device), "hipSetDevice");
     if (st) return st;
@@ -218,6 +223,7 @@ lt_status lt_batch_status(lt_batch* b, void* stream, int32_t* status) {
 }
 
 lt_status lt_batch_destroy(lt_batch* b) {
+    lt::CallScope call_scope_("lt_batch_destroy");
     if (!b) return LT_OK;
     (void)hipSetDevice(b->ctx->device);
     (void)hipDeviceSynchronize();

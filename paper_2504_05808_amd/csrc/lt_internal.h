@@ -133,6 +133,16 @@ namespace lt {
 
 // Host helpers (api.hip).
 lt_status set_error(lt_status s, const char* fmt, ...);
+
+// Scope of an exported call on the host: names the call in the LT_LOG lines (level 2
+// prints the call with its volume arguments; level 1 prints every error status with
+// the name of the call it came from).  Restores the enclosing name on exit.
+struct CallScope {
+    const char* prev;
+    explicit CallScope(const char* fn, int ndim = 0, const int64_t* shape = nullptr, int dtype = -1,
+                       long long max_label = -1);
+    ~CallScope();
+};
 lt_status hip_check(hipError_t e, const char* what);
 lt_status ensure_scratch(lt_ctx* ctx, size_t bytes);
 // hipMalloc through the allocation fault injection (LT_FAULT_INJECT=alloc[:N]).

@@ -460,6 +460,7 @@ using namespace lt;
 extern "C" {
 
 lt_status lt_mlp_create(lt_ctx* ctx, uint64_t seed, lt_mlp** out) {
+    lt::CallScope call_scope_("lt_mlp_create");
     if (!ctx || !out) return set_error(LT_E_ARG, "ctx or out is NULL");
     *out = nullptr;
     lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -512,6 +513,7 @@ lt_status lt_mlp_create(lt_ctx* ctx, uint64_t seed, lt_mlp** out) {
 }
 
 lt_status lt_mlp_destroy(lt_mlp* p) {
+    lt::CallScope call_scope_("lt_mlp_destroy");
     if (!p) return LT_OK;
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
@@ -525,6 +527,7 @@ lt_status lt_mlp_destroy(lt_mlp* p) {
 
 lt_status lt_mlp_set_normalization(lt_mlp* p, const float* mean, const float* stdev, float target_shift,
                                    float target_scale) {
+    lt::CallScope call_scope_("lt_mlp_set_normalization");
     if (!p || !mean || !stdev) return set_error(LT_E_ARG, "NULL argument");
     if (!(target_scale > 0.f)) return set_error(LT_E_ARG, "target_scale must be positive");
     for (int k = 0; k < MLP_IN; ++k) {
@@ -537,6 +540,7 @@ lt_status lt_mlp_set_normalization(lt_mlp* p, const float* mean, const float* st
 }
 
 lt_status lt_mlp_set_guard(lt_mlp* p, const float* fmin, const float* fmax, float max_abs_delta) {
+    lt::CallScope call_scope_("lt_mlp_set_guard");
     if (!p || !fmin || !fmax) return set_error(LT_E_ARG, "NULL argument");
     memcpy(p->fmin, fmin, sizeof(p->fmin));
     memcpy(p->fmax, fmax, sizeof(p->fmax));
@@ -546,6 +550,7 @@ lt_status lt_mlp_set_guard(lt_mlp* p, const float* fmin, const float* fmax, floa
 
 lt_status lt_mlp_train_step(lt_mlp* p, const float* x, const float* y, int B, float lr, float weight_decay,
                             float* loss_out, void* stream) {
+    lt::CallScope call_scope_("lt_mlp_train_step");
     if (!p || !x || !y) return set_error(LT_E_ARG, "NULL argument");
     if (B <= 0 || B % 16) return set_error(LT_E_ARG, "batch size must be a positive multiple of 16");
     lt_status st = hip_check(hipSetDevice(p->ctx->device), "hipSetDevice");
@@ -575,6 +580,7 @@ lt_status lt_mlp_train_step(lt_mlp* p, const float* x, const float* y, int B, fl
 }
 
 lt_status lt_mlp_infer(lt_mlp* p, const float* x, int B, float* delta, void* stream) {
+    lt::CallScope call_scope_("lt_mlp_infer");
     if (!p || (B > 0 && (!x || !delta))) return set_error(LT_E_ARG, "NULL argument");
     if (B <= 0) return LT_OK;
     lt_status st = hip_check(hipSetDevice(p->ctx->device), "hipSetDevice");
@@ -591,6 +597,7 @@ lt_status lt_mlp_infer(lt_mlp* p, const float* x, int B, float* delta, void* str
 
 lt_status lt_mlp_features(lt_ctx* ctx, const float* hist32, const uint64_t* volume, const float* mean_lt,
                           uint32_t n, float* x, void* stream) {
+    lt::CallScope call_scope_("lt_mlp_features");
     if (!ctx || (n > 0 && (!hist32 || !volume || !mean_lt || !x))) return set_error(LT_E_ARG, "NULL argument");
     if (n == 0) return LT_OK;
     lt_status st = hip_check(hipSetDevice(ctx->device), "hipSetDevice");
@@ -601,6 +608,7 @@ lt_status lt_mlp_features(lt_ctx* ctx, const float* hist32, const uint64_t* volu
 
 lt_status lt_mlp_correct(lt_mlp* p, const float* x, const float* s_lt, int n, float* delta_scratch,
                          float* s_corr, uint32_t* n_fallback, void* stream) {
+    lt::CallScope call_scope_("lt_mlp_correct");
     if (!p || (n > 0 && (!x || !s_lt || !delta_scratch || !s_corr || !n_fallback)))
         return set_error(LT_E_ARG, "NULL argument");
     if (n <= 0) return LT_OK;
@@ -618,6 +626,7 @@ lt_status lt_mlp_correct(lt_mlp* p, const float* x, const float* s_lt, int n, fl
 size_t lt_mlp_state_size(void) { return (3 * (size_t)N_PARAM + 4 * MLP_IN + 3 + 2) * sizeof(float); }
 
 lt_status lt_mlp_get_state(lt_mlp* p, void* blob, size_t bytes) {
+    lt::CallScope call_scope_("lt_mlp_get_state");
     if (!p || !blob || bytes < lt_mlp_state_size()) return set_error(LT_E_WORKSPACE, "state buffer too small");
     float* f = (float*)blob;
     lt_status st = hip_check(hipSetDevice(p->ctx->device), "hipSetDevice");
@@ -643,6 +652,7 @@ lt_status lt_mlp_get_state(lt_mlp* p, void* blob, size_t bytes) {
 }
 
 lt_status lt_mlp_set_state(lt_mlp* p, const void* blob, size_t bytes) {
+    lt::CallScope call_scope_("lt_mlp_set_state");
     if (!p || !blob || bytes < lt_mlp_state_size()) return set_error(LT_E_WORKSPACE, "state buffer too small");
     const float* f = (const float*)blob;
     lt_status st = hip_check(hipSetDevice(p->ctx->device), "hipSetDevice");
@@ -669,6 +679,7 @@ lt_status lt_mlp_set_state(lt_mlp* p, const void* blob, size_t bytes) {
 
 lt_status lt_bf16_gemm(int M, int N, int K, const uint16_t* A, int lda, int trans_a, const uint16_t* B,
                        int ldb, int trans_b, float* C, int ldc, void* stream) {
+    lt::CallScope call_scope_("lt_bf16_gemm");
     if (M < 0 || N < 0 || K < 0 || M % 16 || N % 16 || K % 16)
         return set_error(LT_E_SHAPE, "M, N and K must be non-negative multiples of 16");
     if (M == 0 || N == 0) return LT_OK;
@@ -680,6 +691,7 @@ lt_status lt_bf16_gemm(int M, int N, int K, const uint16_t* A, int lda, int tran
 // Device pointers to the FP32 master weights and gradients (N_PARAM floats each) and
 // the parameter count.
 lt_status lt_mlp_buffers(lt_mlp* p, float** weights, float** grads, int* n_param) {
+    lt::CallScope call_scope_("lt_mlp_buffers");
     if (!p) return set_error(LT_E_ARG, "mlp is NULL");
     if (weights) *weights = p->w;
     if (grads) *grads = p->g;
@@ -688,6 +700,7 @@ lt_status lt_mlp_buffers(lt_mlp* p, float** weights, float** grads, int* n_param
 }
 
 lt_status lt_mlp_read(lt_mlp* p, int which, float* host, size_t n) {
+    lt::CallScope call_scope_("lt_mlp_read");
     if (!p || !host) return set_error(LT_E_ARG, "NULL argument");
     if (which < 0 || which > 3) return set_error(LT_E_ARG, "which must be 0..3");
     if (n < (size_t)N_PARAM) return set_error(LT_E_WORKSPACE, "host buffer holds fewer than n_param floats");
