@@ -38,7 +38,10 @@
  *     per call that takes a volume (name, shape, label type, label bound);
  *     LT_FAULT_INJECT=alloc makes every device allocation of the library fail
  *     with LT_E_ALLOC, alloc:N after N more successes (tests of the failure
- *     paths).  Both are read at every use.
+ *     paths); LT_SPILL_CAP=K caps each spill region and the shared spill pool of
+ *     the 3D local-thickness pass at K words (0: every front longer than four
+ *     entries is rescanned by the paint pass instead; same results, slower; tests
+ *     of that path).  All are read at every use.
  */
 #ifndef LT_H
 #define LT_H

@@ -26,6 +26,8 @@
 // Work items are (object, 64x64 or 32x64 tile of the object's y-x bounding box) and run
 // slice by slice over the object's z extent; the source columns of a tile are the
 // tile grown by the object's largest ball reach, clipped to its bounding box.
+#include <stdlib.h>
+
 #include <mutex>
 
 #include "lt_internal.h"
@@ -475,7 +477,7 @@ __global__ void __launch_bounds__(256)
 fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
          const int32_t* __restrict__ colmax, uint32_t* __restrict__ zf, uint32_t* __restrict__ spill,
          uint32_t* __restrict__ work, uint32_t* __restrict__ nwork, uint32_t wcap, SpillPool pool,
-         uint32_t* __restrict__ bmap, int wz = 1) {
+         uint32_t* __restrict__ bmap, uint32_t region_cap, int wz = 1) {
     extern __shared__ __align__(16) uint32_t S[];
     __shared__ int s_cm[64];
     __shared__ int s_bm[128];                         // per slice: bound on the block's front values
@@ -498,7 +500,7 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
     uint32_t* tile = S + 4 * FZ_WAVE;
     uint32_t* list = S + wid * FZ_WAVE;               // compacted keys, then ranked pairs
     int* dq = (int*)(list + 2 * FZ_LIST);             // D of the entries 3, 7, 11, ... by rank
-    const uint32_t cap = (uint32_t)(SPILL_ROW_SLICE * chunk);
+    const uint32_t cap = min((uint32_t)(SPILL_ROW_SLICE * chunk), region_cap);
     uint32_t* region = spill + ((size_t)blockIdx.z * ny + y) * gridDim.x * (size_t)cap + (size_t)blockIdx.x * cap;
     const unsigned long long below = (1ull << lane) - 1ull;
     int bacc0 = 0, bacc1 = 0;                         // the wave's group bounds of slices c0 + lane, + 64
@@ -1582,7 +1584,18 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     int32_t* colmax = (int32_t*)(base + lay.colmax);
     uint32_t* work = (uint32_t*)(base + lay.work);
     uint32_t* bmap = (uint32_t*)(base + lay.bmap);
-    const SpillPool pool{(uint32_t*)(base + lay.pool), (unsigned long long*)(counter + 4), lay.pool_words};
+    // LT_SPILL_CAP (environment, read at every call) caps each block's spill region and
+    // the pool at that many words: with 0 every front longer than ZF_PLANES is rescanned
+    // by the paint pass (the fallback kept for full spill space), which tests of that
+    // path use.  Same results.
+    size_t pool_words = lay.pool_words;
+    uint32_t region_cap = 0xffffffffu;
+    if (const char* e = getenv("LT_SPILL_CAP")) {
+        const unsigned long long c = strtoull(e, nullptr, 10);
+        pool_words = std::min(pool_words, (size_t)c);
+        region_cap = (uint32_t)std::min(c, 0xffffffffull);
+    }
+    const SpillPool pool{(uint32_t*)(base + lay.pool), (unsigned long long*)(counter + 4), pool_words};
     const size_t ncol = g.ndim == 3 ? (size_t)g.ny * g.nx : 0;
     const int chunk = ctx->tune.front_chunk > 0 ? ctx->tune.front_chunk : 64;
     const uint32_t nlab = max_label + 1;
@@ -1614,10 +1627,10 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             const dim3 grid((g.nx + 63) / 64, g.ny, (g.nz + chunk - 1) / chunk);
             if (w)
                 fronts3d<true><<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill,
-                                                                      work, counter + 2, lay.wcap, pool, bmap, sp.wz);
+                                                                      work, counter + 2, lay.wcap, pool, bmap, region_cap, sp.wz);
             else
                 fronts3d<<<grid, 256, fronts3d_lds(chunk), s>>>(kd, g.nx, g.ny, g.nz, chunk, colmax, zf, spill,
-                                                                work, counter + 2, lay.wcap, pool, bmap);
+                                                                work, counter + 2, lay.wcap, pool, bmap, region_cap);
         }
         {
             // columns with more listed centres than the front pass holds (objects of

@@ -218,3 +218,36 @@ def test_banded_paint_bit_exact(gpu, weights):
         np.testing.assert_array_equal(got[k][:3], ref[k])
     for k in FLOAT_KEYS:
         np.testing.assert_allclose(got[k][1:3], ref[k][1:3], rtol=RTOL, atol=0, err_msg=k)
+
+
+@pytest.mark.parametrize("case", ["ellipsoids", "grains", "grains_weighted", "ball_r80"])
+def test_rescan_fallback_bit_exact(gpu, case, monkeypatch):
+    """LT_SPILL_CAP=0 leaves the front pass no spill space, so every front longer than
+    four entries is rescanned by the paint pass (the fallback kept for full spill
+    space), in the plain and the banded launch: D, LT and the measures equal the
+    normal run's bit for bit (the normal run is checked against the oracle by the
+    other tests)."""
+    torch, lt = gpu
+    w = None
+    if case == "ellipsoids":
+        lab, _ = synth.cfg2()
+    elif case.startswith("grains"):
+        lab = _two_grains()
+        w = (4, 1, 1) if case == "grains_weighted" else None
+    else:
+        lab = np.pad(synth.ball_mask(80)[0].astype(np.int32), 2)
+    t = torch.from_numpy(np.ascontiguousarray(lab)).cuda()
+    ml = int(lab.max())
+
+    def run():
+        out = lt.pipeline(t, ml) if w is None else lt.pipeline_aniso(t, ml, w)
+        lt.default_context().sync_status()
+        return _to_host(*out)
+
+    _note(f"rescan fallback: {case} shape={lab.shape}")
+    ref = run()
+    monkeypatch.setenv("LT_SPILL_CAP", "0")
+    got = run()
+    monkeypatch.delenv("LT_SPILL_CAP")
+    for k in ref:
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
