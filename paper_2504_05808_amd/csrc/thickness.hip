@@ -782,17 +782,19 @@ fronts3d_long(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
 // ------------------------------------------------------------------ 2D pixel pass
 
 // One thread per pixel: background LT = 0, centre prune (8 neighbours), plane 0 =
-// D | bit 31 for kept centres (a kept pixel is its own disc), per-label maximum D.
+// D | bit 31 for kept centres (a kept pixel is its own disc), per-label maximum D, and
+// the banded launch's group bounds (largest kept D per row and 64-column group).
 template <typename L, bool W = false>
 __global__ void __launch_bounds__(256)
 pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny,
          uint32_t max_label, const int32_t* __restrict__ tab, uint32_t* __restrict__ zf,
-         int32_t* __restrict__ lt, int32_t* __restrict__ maxd, int wy = 1, int wx = 1) {
+         int32_t* __restrict__ lt, int32_t* __restrict__ maxd, uint32_t* __restrict__ bmap, int wy = 1,
+         int wx = 1) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const size_t i = (size_t)y * nx + x;
     const int d = x < nx ? D[i] : 0;
-    bool keep = false;
+    bool keep = false, kept = false;
     uint32_t l = 0;
     if (d > 0) {
         const L raw = lab[i];
@@ -820,17 +822,24 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
             if (W) keep = keep && mc[2] <= (in_tab ? tab[2 * (PRUNE_DCAP + 1) + d] : prune_bound(d, k2));
         }
         zf[i] = keep ? ((uint32_t)d | 0x80000000u) : 0u;
+        kept = keep;
         if (label_negative(raw) || (uint64_t)raw > max_label) keep = false;
         l = (uint32_t)raw;
     } else if (x < nx) {
         lt[i] = 0;
     }
+    // group bound of the banded paint launch: the largest kept D of the wave's 64 pixels
+    // (one row, an aligned group of 64 columns)
+    int gb = kept ? d : 0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) gb = max(gb, __shfl_xor(gb, off, 64));
+    if ((threadIdx.x & 63) == 0 && x < nx) bmap[(size_t)y * ((nx + 63) / 64) + (x >> 6)] = (uint32_t)gb;
     wave_label_max(l, keep, d, maxd);              // every lane reaches this call
 }
 
 // ------------------------------------------------------------------ planning
 
-// Objects whose balls reach at least this far along y or x (3D) are painted by the
+// Objects whose balls reach at least this far along y or x are painted by the
 // banded launch: value bands with a tile floor (their source region spans several
 // tiles' worth of columns).
 constexpr int BAND_REACH = 32;
@@ -1343,6 +1352,10 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                             column(lc, ec, sx, sy, rowi, need, fl);
                         }
                         }
+                        if (NDIM == 2 && nlist) {             // 2D lists hold one source row
+                            disc_flush<NDIM, W>(t, nlist, sy, lane);
+                            nlist = 0;
+                        }
                     }
                     if (nlist) disc_flush<NDIM, W>(t, nlist, sy0, lane);
                     nlist = 0;
@@ -1513,7 +1526,7 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.pool = at;    at += align256(o.pool_words * sizeof(uint32_t));
     // bound on the front values per (slice, row, 64-column group): the largest kept D
     // of the group's columns that have a front in the slice
-    o.bmap = at;    at += g.ndim == 3 ? align256((size_t)g.nz * g.ny * ((g.nx + 63) / 64) * sizeof(uint32_t)) : 0;
+    o.bmap = at;    at += align256((size_t)g.nz * g.ny * ((g.nx + 63) / 64) * sizeof(uint32_t));
     o.total = at;
     return o;
 }
@@ -1549,7 +1562,13 @@ int paint_tile_rows(lt_ctx* ctx) {
                              (const void*)paint_tiles<3, uint32_t, false, true>,
                              (const void*)paint_tiles<3, uint16_t, true, true>,
                              (const void*)paint_tiles<3, int32_t, true, true>,
-                             (const void*)paint_tiles<3, uint32_t, true, true>};
+                             (const void*)paint_tiles<3, uint32_t, true, true>,
+                             (const void*)paint_tiles<2, uint16_t, false, true>,
+                             (const void*)paint_tiles<2, int32_t, false, true>,
+                             (const void*)paint_tiles<2, uint32_t, false, true>,
+                             (const void*)paint_tiles<2, uint16_t, true, true>,
+                             (const void*)paint_tiles<2, int32_t, true, true>,
+                             (const void*)paint_tiles<2, uint32_t, true, true>};
         for (const void* f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PAINT_DYN64);
     });
@@ -1649,15 +1668,15 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
         ProfScope _p(ctx, s, "pixels2d");
         if (w)
             pixels2d<L, true><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(lab, D, g.nx, g.ny, max_label,
-                                                                                  tabw, zf, lt, maxd, sp.wy, sp.wx);
+                                                                                  tabw, zf, lt, maxd, bmap, sp.wy, sp.wx);
         else
             pixels2d<L><<<dim3((g.nx + 255) / 256, g.ny), dim3(256), 0, s>>>(lab, D, g.nx, g.ny, max_label,
-                                                                            ctx->d_prune2, zf, lt, maxd);
+                                                                            ctx->d_prune2, zf, lt, maxd, bmap);
     }
     const int tile_y = paint_tile_rows(ctx);
-    // objects with balls reaching BAND_REACH or more along y or x (3D) take the banded
-    // launch: largest D above BAND_REACH^2 times the smaller in-plane squared spacing
-    const int band_d = g.ndim == 3 ? BAND_REACH * BAND_REACH * std::min(sp.wy, sp.wx) : INT_MAX;
+    // objects with balls reaching BAND_REACH or more along y or x take the banded launch:
+    // largest D above BAND_REACH^2 times the smaller in-plane squared spacing
+    const int band_d = BAND_REACH * BAND_REACH * std::min(sp.wy, sp.wx);
     {
         ProfScope _p(ctx, s, "plan_tiles");
         plan_tiles<<<1, 1024, 0, s>>>(bb, maxd, nlab, tile_y, band_d, toff, toff_big, counter);
@@ -1691,6 +1710,17 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
                                                            tile_y, counter, lt, spill, pool.base, bmap, chunk, ms, D);
     } else {
+        {
+            ProfScope _p(ctx, s, "paint_tiles_banded");
+            if (w)
+                paint_tiles<2, L, true, true><<<blocks, threads, lds, s>>>(
+                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
+                    bmap, chunk, ms, D, sp);
+            else
+                paint_tiles<2, L, false, true><<<blocks, threads, lds, s>>>(
+                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
+                    bmap, chunk, ms, D);
+        }
         ProfScope _p(ctx, s, "paint_tiles");
         if (w)
             paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,

@@ -251,3 +251,42 @@ def test_rescan_fallback_bit_exact(gpu, case, monkeypatch):
     monkeypatch.delenv("LT_SPILL_CAP")
     for k in ref:
         np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+
+
+def _two_ellipses():
+    """Two touching ellipses (label 2 overwrites where they meet): label 1 with largest
+    D 1690 (banded launch), label 2 with 292 (plain launch)."""
+    a, _ = synth.ellipse_mask(62.0, 41.0, 0.3)
+    b, _ = synth.ellipse_mask(26.0, 17.0, 1.1)
+    lab = np.zeros((max(a.shape[0], b.shape[0]) + 4, a.shape[1] + b.shape[1] + 4), np.int32)
+    lab[2:2 + a.shape[0], 2:2 + a.shape[1]][a] = 1
+    o = 2 + a.shape[1] - 5
+    lab[2:2 + b.shape[0], o:o + b.shape[1]][b] = 2
+    return lab
+
+
+@pytest.mark.parametrize("weights", [None, (1, 4)])
+def test_banded_paint_2d_bit_exact(gpu, weights):
+    """The banded launch in 2D (every kept pixel is its own disc): D, LT and the
+    per-object measures against the oracle, element by element."""
+    torch, lt = gpu
+    lab = _two_ellipses()
+    _note(f"two ellipses shape={lab.shape} weights={weights}")
+    D, LT, _ = O.fields(lab, threads=16, weights=weights)
+    assert int(D[lab == 1].max()) > 1024 * (1 if weights is None else min(weights))
+    if weights is None:
+        got = _run_both(gpu, lab)
+    else:
+        t = torch.from_numpy(lab).cuda()
+        got = _to_host(*lt.pipeline_aniso(t, 2, weights))
+        lt.default_context().sync_status()
+    np.testing.assert_array_equal(got["dist_sq"], D)
+    np.testing.assert_array_equal(got["lt_sq"], LT)
+    sums = O.object_sums(lab, LT, 2)
+    vs = 1.0 if weights is None else math.sqrt(float(np.prod(weights)))
+    ref = dict(sums)
+    ref.update(O.closed_forms(sums, 2, voxel_size=vs))
+    for k in ("volume", "shell_count", "max_lt_sq"):
+        np.testing.assert_array_equal(got[k][:3], ref[k])
+    for k in FLOAT_KEYS:
+        np.testing.assert_allclose(got[k][1:3], ref[k][1:3], rtol=RTOL, atol=0, err_msg=k)
