@@ -374,11 +374,16 @@ lt_status lt_ctx_create(lt_ctx** out, int device) {
         build_prune_tables(3, g_tab3);
         build_prune_tables(2, g_tab2);
     });
-    size_t b3 = g_tab3.size() * sizeof(int32_t), b2 = g_tab2.size() * sizeof(int32_t);
+    // the 3D tables go to the device interleaved, {T_1[d], T_2[d], T_3[d], 0} per d, so
+    // that the prune reads a centre's three thresholds with one 16-byte load
+    std::vector<int32_t> tab3i((size_t)4 * (PRUNE_DCAP + 1), 0);
+    for (int d = 0; d <= PRUNE_DCAP; ++d)
+        for (int k = 0; k < 3; ++k) tab3i[(size_t)4 * d + k] = g_tab3[(size_t)k * (PRUNE_DCAP + 1) + d];
+    size_t b3 = tab3i.size() * sizeof(int32_t), b2 = g_tab2.size() * sizeof(int32_t);
     if ((st = device_alloc((void**)&c->d_err, sizeof(uint32_t), "hipMalloc(err)")) ||
         (st = device_alloc((void**)&c->d_prune3, b3, "hipMalloc(tab3)")) ||
         (st = device_alloc((void**)&c->d_prune2, b2, "hipMalloc(tab2)")) ||
-        (st = hip_check(hipMemcpy(c->d_prune3, g_tab3.data(), b3, hipMemcpyHostToDevice), "copy tab3")) ||
+        (st = hip_check(hipMemcpy(c->d_prune3, tab3i.data(), b3, hipMemcpyHostToDevice), "copy tab3")) ||
         (st = hip_check(hipMemcpy(c->d_prune2, g_tab2.data(), b2, hipMemcpyHostToDevice), "copy tab2")) ||
         (st = hip_check(hipMemset(c->d_err, 0, sizeof(uint32_t)), "clear err")) ||
         (st = static_scratch_lookup(device, &c->static_scratch))) {

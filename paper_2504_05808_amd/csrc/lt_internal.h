@@ -114,7 +114,7 @@ struct lt_ctx {
     int n_cu = 0;
     size_t lds_per_block = 0;
     uint32_t* d_err = nullptr;          // device error word
-    int32_t* d_prune3 = nullptr;        // [3][PRUNE_DCAP + 1] (|o|^2 = 1, 2, 3)
+    int32_t* d_prune3 = nullptr;        // [PRUNE_DCAP + 1][4]: T(|o|^2 = 1, 2, 3) for d, then 0
     int32_t* d_prune2 = nullptr;        // [2][PRUNE_DCAP + 1] (|o|^2 = 1, 2)
     lt::Scratch scratch;                // grows on demand, freed by lt_ctx_destroy
     void* static_scratch = nullptr;     // this device's copy of the fixed scratch of

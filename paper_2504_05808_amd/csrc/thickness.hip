@@ -277,11 +277,19 @@ prune3d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int ny
             const L raw = lab[i];
             keep = true;
             if (!W) {
-                // thresholds from the tables, or beyond them the containment bound
-                const bool in_tab = d <= PRUNE_DCAP;
-                const int a1 = in_tab ? tab[d] : prune_bound(d, 1);
-                const int a2 = in_tab ? tab[(PRUNE_DCAP + 1) + d] : prune_bound(d, 2);
-                const int a3 = in_tab ? tab[2 * (PRUNE_DCAP + 1) + d] : prune_bound(d, 3);
+                // thresholds from the (interleaved) tables, or beyond them the
+                // containment bound
+                int a1, a2, a3;
+                if (d <= PRUNE_DCAP) {
+                    const int4 a = ((const int4*)tab)[d];
+                    a1 = a.x;
+                    a2 = a.y;
+                    a3 = a.z;
+                } else {
+                    a1 = prune_bound(d, 1);
+                    a2 = prune_bound(d, 2);
+                    a3 = prune_bound(d, 3);
+                }
                 // largest D over the face, edge and corner neighbours: the centre is
                 // dropped when one class exceeds its table value
                 int m1 = 0, m2 = 0, m3 = 0;
