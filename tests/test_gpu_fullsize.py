@@ -196,7 +196,8 @@ def _two_grains():
 @pytest.mark.parametrize("weights", [None, (4, 1, 1)])
 def test_banded_paint_bit_exact(gpu, weights):
     """Objects of large reach are painted in value bands with a tile floor: D, LT and
-    the per-object measures against the oracle, element by element."""
+    the per-object measures against the oracle, element by element; the same volume
+    as int32 and uint32 labels gives the same fields."""
     torch, lt = gpu
     lab = _two_grains()
     _note(f"two grains shape={lab.shape} weights={weights}")
@@ -210,6 +211,12 @@ def test_banded_paint_bit_exact(gpu, weights):
         lt.default_context().sync_status()
     np.testing.assert_array_equal(got["dist_sq"], D)
     np.testing.assert_array_equal(got["lt_sq"], LT)
+    for dt in (np.int32, np.uint32):
+        t2 = torch.from_numpy(lab.astype(dt)).cuda()
+        other = _to_host(*(lt.pipeline(t2, 2) if weights is None else lt.pipeline_aniso(t2, 2, weights)))
+        lt.default_context().sync_status()
+        for k in other:
+            np.testing.assert_array_equal(other[k], got[k], err_msg=f"{np.dtype(dt).name}: {k}")
     sums = O.object_sums(lab, LT, 2)
     vs = 1.0 if weights is None else math.sqrt(float(np.prod(weights)))
     ref = dict(sums)
