@@ -15,17 +15,23 @@
 //     only the Pareto front over (value, residual) is kept, since a dominated pair
 //     is covered by the dominating one in every later step.  A positive residual
 //     means the ball holds (z, y, x) itself, so every pair of a front belongs to
-//     the label of that voxel.  Fronts are computed by one thread per column walking
-//     z (coalesced across x) and stored in up to four dense planes; a larger front
-//     is flagged and the paint pass rescans that column's kept centres.
+//     the label of that voxel.  Fronts are computed per column with lanes along z
+//     and stored in up to four dense planes; a longer front goes whole to a spill
+//     region of its block or to a shared pool (only with no spill space left is the
+//     column rescanned by the paint pass); columns with more kept centres than the
+//     front pass lists in LDS are finished by a long-list pass.
 //  3. Disc painting.  In slice z, a front pair is a disc of squared radius b around
 //     (y, x) carrying value D; each disc row is an interval along x.  Intervals are
 //     max-painted into an LDS sparse table (two atomics per interval: the interval
 //     is covered by two blocks of length 2^k), and a push-down over the levels
 //     yields the per-voxel maximum.
+//  4. Bands (objects of large reach).  Source groups are taken in bands of a bound
+//     on their values, and a group or disc whose bound does not exceed the smallest
+//     value already painted over the object's cells of the tile is skipped.
 // Work items are (object, 64x64 or 32x64 tile of the object's y-x bounding box) and run
-// slice by slice over the object's z extent; the source columns of a tile are the
-// tile grown by the object's largest ball reach, clipped to its bounding box.
+// slice by slice over the object's z extent (objects of large reach: 16 slices per
+// item); the source columns of a tile are the tile grown by the object's largest ball
+// reach, clipped to its bounding box.
 #include <stdlib.h>
 
 #include <mutex>
