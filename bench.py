@@ -500,7 +500,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path shards by "
-              "independent objects but no multi-GPU run is part of this build.", file=sys.stderr)
+              "independent objects, and this benchmark measures one GPU's throughput.", file=sys.stderr)
         sys.exit(2)
     if args.batch:
         batch_bench(args)
