@@ -1093,8 +1093,9 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             const int32_t* __restrict__ kd, const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
             const uint32_t* __restrict__ toff, uint32_t nlab, int nx, int ny, int nz, int tile_y,
             uint32_t* __restrict__ counter, int32_t* __restrict__ lt, const uint32_t* __restrict__ spill,
-            const uint32_t* __restrict__ pool, const uint32_t* __restrict__ bmap, int chunk, MeasureSums ms,
-            const int32_t* __restrict__ Dmap, Spacing spc = Spacing()) {
+            const uint32_t* __restrict__ pool, const uint32_t* __restrict__ bmap,
+            const int32_t* __restrict__ colmax, int chunk, MeasureSums ms, const int32_t* __restrict__ Dmap,
+            Spacing spc = Spacing()) {
     // dynamic LDS: the sparse table [TILE_LEVELS][tile_y][TILE_STRIDE], then one disc
     // list per wave
     extern __shared__ uint32_t M[];
@@ -1357,8 +1358,21 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                             int bmv = bmr[0];
 #pragma unroll
                             for (int q = 1; q < BM_CH; ++q) bmv = u == q ? bmr[q] : bmv;
-                            const bool go = in && bmv >= lo_b && bmv < hi_b && bmv > fl;
+                            // a group is visited in every band its bound reaches; in 3D each
+                            // lane then takes its column in the band of the column's largest
+                            // kept D (no smaller than any value its discs carry, no larger than
+                            // the group bound of a slice where it has discs), so every column
+                            // is painted in one band and only columns reaching it in the first
+                            bool go = in && bmv >= lo_b && bmv > fl;
                             if (!__ballot(go)) continue;
+                            if (NDIM == 3) {
+                                const int cml = go ? colmax[(size_t)sy * nx + sx] : 0;
+                                go = go && cml >= lo_b && cml < hi_b && cml > fl;
+                                if (!__ballot(go)) continue;
+                            } else {
+                                go = go && bmv < hi_b;
+                                if (!__ballot(go)) continue;
+                            }
                             const int ddx = max(max(t.tx0 - sx, sx - (t.tx0 + t.W - 1)), 0);
                             const int need = rowd + (W ? spc.wx * ddx * ddx : ddx * ddx);
                             const L lc = go ? lab[rowi + sx] : L(0);
@@ -1709,40 +1723,42 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             if (w)
                 paint_tiles<3, L, true, true><<<blocks, threads, lds, s>>>(
                     lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
-                    pool.base, bmap, chunk, ms, D, sp);
+                    pool.base, bmap, colmax, chunk, ms, D, sp);
             else
                 paint_tiles<3, L, false, true><<<blocks, threads, lds, s>>>(
                     lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
-                    pool.base, bmap, chunk, ms, D);
+                    pool.base, bmap, colmax, chunk, ms, D);
         }
         ProfScope _p(ctx, s, "paint_tiles");
         if (w)
             paint_tiles<3, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
-                                                                 tile_y, counter, lt, spill, pool.base, bmap, chunk,
-                                                                 ms, D, sp);
+                                                                 tile_y, counter, lt, spill, pool.base, bmap, colmax,
+                                                                 chunk, ms, D, sp);
         else
             paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
-                                                           tile_y, counter, lt, spill, pool.base, bmap, chunk, ms, D);
+                                                           tile_y, counter, lt, spill, pool.base, bmap, colmax, chunk,
+                                                           ms, D);
     } else {
         {
             ProfScope _p(ctx, s, "paint_tiles_banded");
             if (w)
                 paint_tiles<2, L, true, true><<<blocks, threads, lds, s>>>(
                     lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
-                    bmap, chunk, ms, D, sp);
+                    bmap, nullptr, chunk, ms, D, sp);
             else
                 paint_tiles<2, L, false, true><<<blocks, threads, lds, s>>>(
                     lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
-                    bmap, chunk, ms, D);
+                    bmap, nullptr, chunk, ms, D);
         }
         ProfScope _p(ctx, s, "paint_tiles");
         if (w)
             paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
-                                                                 tile_y, counter, lt, spill, pool.base, bmap, chunk,
-                                                                 ms, D, sp);
+                                                                 tile_y, counter, lt, spill, pool.base, bmap, nullptr,
+                                                                 chunk, ms, D, sp);
         else
             paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1, tile_y,
-                                                           counter, lt, spill, pool.base, bmap, chunk, ms, D);
+                                                           counter, lt, spill, pool.base, bmap, nullptr, chunk, ms,
+                                                           D);
     }
     return hip_check(hipGetLastError(), "thickness launch");
 }
