@@ -858,6 +858,7 @@ pixels2d(const L* __restrict__ lab, const int32_t* __restrict__ D, int nx, int n
 // tiles' worth of columns).
 constexpr int BAND_REACH = 32;
 constexpr int BAND_ZCHUNK = 16;      // slices per banded work item (a large object alone fills the chip)
+constexpr int NBANDS = 3;            // value bands of the banded launch
 
 // Exclusive scans over labels of the number of paint items of each present object,
 // split by size: objects whose largest D exceeds band_d (balls reaching BAND_REACH or
@@ -1177,6 +1178,8 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         // one is unpainted; INT_MAX when the slice holds none).
         auto tile_floor = [&](int slot, int pz) -> int {
             __syncthreads();                            // every wave's discs are in the table
+            // the other slot is next band's: every thread has read its last floor
+            if (tid == 0) s_floor[slot ^ 1] = INT_MAX;
             for (int row = wid; row < t.H; row += nwaves) {
                 uint32_t val[TILE_LEVELS];
 #pragma unroll
@@ -1325,21 +1328,26 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             };
             if constexpr (BAND) {
                 // Objects of large reach: the source groups (one source row x 64 columns)
-                // in three bands of their bound on the front values (the front pass's
-                // group bounds) -- those reaching the object's largest D, those of at
-                // least half of it, the rest -- with the tile's floor (smallest value
-                // painted so far over the object's cells in this slice) taken after the
-                // first two.  A group whose bound does not exceed the floor, and any disc
-                // whose value does not, cannot raise a cell and is skipped.
+                // in NBANDS bands of value, from the object's largest D down, with the
+                // tile's floor (smallest value painted so far over the object's cells in
+                // this slice) taken after every band but the last.  A group whose bound
+                // does not exceed the floor, and any disc whose value does not, cannot
+                // raise a cell and is skipped.
                 const uint32_t* bms = bmap + (size_t)pz * ny * ngroups;
                 int fl = 0;
                 // group bounds of a source row, loaded together BM_CH chunks of 64
                 // columns at a time (one round trip for rows up to 384 columns)
                 constexpr int BM_CH = 6;
                 const int nch = (sx1 - sx0 + 63) >> 6;
-                for (int band = 0; band < 3; ++band) {
-                    const int lo_b = band == 0 ? mdl : band == 1 ? (mdl >> 1) : INT_MIN;
-                    const int hi_b = band == 0 ? INT_MAX : band == 1 ? mdl : (mdl >> 1);
+                for (int band = 0; band < NBANDS; ++band) {
+                    // bands from the object's largest D down: [mdl, inf), then equal steps
+                    // of mdl (with three bands [mdl / 2, mdl) and the rest)
+                    const int lo_b = band == 0 ? mdl : band == NBANDS - 1 ? INT_MIN
+                                                                          : (int)(((long long)mdl * (NBANDS - 1 - band)) / (NBANDS - 1));
+                    const int hi_b = band == 0 ? INT_MAX
+                                               : (int)(((long long)mdl * (NBANDS - band)) / (NBANDS - 1));
+                    // no value of this band, or a later one, exceeds the floor: done
+                    if (band > 0 && fl >= hi_b) break;
                     for (int sy = sy0 + wid; sy < sy1; sy += nwaves) {
                         const size_t rowi = ((size_t)pz * ny + sy) * nx;
                         const int ddy = max(max(t.ty0 - sy, sy - (t.ty0 + t.H - 1)), 0);
@@ -1387,7 +1395,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
                     }
                     if (nlist) disc_flush<NDIM, W>(t, nlist, sy0, lane);
                     nlist = 0;
-                    if (band < 2) fl = tile_floor(band, pz);
+                    if (band < NBANDS - 1) fl = tile_floor(band & 1, pz);
                 }
             } else {
                 fetch_row(rfirst);
