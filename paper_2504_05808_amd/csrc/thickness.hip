@@ -860,31 +860,105 @@ constexpr int BAND_REACH = 32;
 constexpr int BAND_ZCHUNK = 16;      // slices per banded work item (a large object alone fills the chip)
 constexpr int NBANDS = 3;            // value bands of the banded launch
 
-// Exclusive scans over labels of the number of paint items of each present object,
-// split by size: objects whose largest D exceeds band_d (balls reaching BAND_REACH or
-// more along y or x) go to toff_big and the banded paint launch, one item per (tile,
-// BAND_ZCHUNK slices); the rest to toff, one item per tile over all its slices.
-// toff and toff_big have nlab + 1 entries; entry nlab is the total.  One block of
-// 1024 threads.
+// Paint work items of the present objects, split by size: objects whose largest D
+// exceeds band_d (balls reaching BAND_REACH or more along y or x) go to toff_big and
+// the banded paint launch, one item per (tile, BAND_ZCHUNK slices); the rest to toff,
+// one item per (tile, run of at most PLAIN_ZCHUNK slices; an object of bz slices is cut
+// into ceil(bz / PLAIN_ZCHUNK) runs of equal length, the last shorter).  Both launches run a persistent grid that
+// takes items in list order, so the lists are ordered by estimated cost, longest
+// first, whatever the numbering of the labels (list scheduling ends evenly when the
+// long items go first): each present object gets a key, the class of its per-item
+// work (slices x rows x columns of an item times the reach of its largest ball, plus
+// one) in steps of a quarter octave; positions are given out key by key from the costliest down (in
+// arrival order within a key), ord[position] = label, and toff / toff_big are
+// exclusive scans over positions of the objects' item counts.  Positions past the
+// present objects hold no items.  toff and toff_big have nlab + 1 entries; entry nlab
+// is the total.  One block of 1024 threads.
+constexpr int PLAN_KEYS = 1024;            // one per thread of the block
+constexpr int PLAIN_ZCHUNK = 24;
+
+__device__ __forceinline__ void plan_items(const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
+                                           uint32_t nlab, int tile_y, int band_d, uint32_t l, uint32_t& c,
+                                           bool& big, int& key) {
+    c = 0u;
+    big = false;
+    key = 0;
+    if (l == 0u || l >= nlab || bb[5 * nlab + l] < 0) return;
+    const int bz = bb[1 * nlab + l] - bb[0 * nlab + l] + 1;
+    const int by = bb[3 * nlab + l] - bb[2 * nlab + l] + 1;
+    const int bx = bb[5 * nlab + l] - bb[4 * nlab + l] + 1;
+    const int ty = (by + tile_y - 1) / tile_y, tx = (bx + TILE_X - 1) / TILE_X;
+    const int md = max(maxd[l], 1);
+    c = (uint32_t)(ty * tx);
+    big = md > band_d;
+    int zi = bz;                                       // slices of one item
+    if (big) {
+        c *= (uint32_t)((bz + BAND_ZCHUNK - 1) / BAND_ZCHUNK);
+        zi = min(bz, BAND_ZCHUNK);
+    } else {
+        const int nzc = (bz + PLAIN_ZCHUNK - 1) / PLAIN_ZCHUNK;
+        c *= (uint32_t)nzc;
+        zi = (bz + nzc - 1) / nzc;
+    }
+    const unsigned long long cost = (unsigned long long)zi * (unsigned long long)((by + ty - 1) / ty) *
+                                    (unsigned long long)((bx + tx - 1) / tx) *
+                                    (unsigned long long)(open_reach(md) + 1);
+    const int e = 63 - __clzll(cost);                  // cost >= 1
+    const int frac = (int)((e >= 2 ? cost >> (e - 2) : cost << (2 - e)) & 3ull);
+    key = min(PLAN_KEYS - 1, (e << 2) | frac);
+}
+
 __global__ void __launch_bounds__(1024)
 plan_tiles(const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd, uint32_t nlab, int tile_y,
-           int band_d, uint32_t* __restrict__ toff, uint32_t* __restrict__ toff_big,
+           int band_d, uint32_t* __restrict__ toff, uint32_t* __restrict__ toff_big, uint32_t* __restrict__ ord,
            uint32_t* __restrict__ counter) {
     __shared__ uint32_t s[2][1024];
+    __shared__ uint32_t s_key[PLAN_KEYS];              // objects per key, then the key's next position
+    __shared__ uint32_t s_np;
     const int t = threadIdx.x;
-    uint32_t running[2] = {0u, 0u};
+    s_key[t] = 0u;
+    __syncthreads();
+    for (uint32_t base = 0; base < nlab; base += 1024) {
+        uint32_t c;
+        bool big;
+        int key;
+        plan_items(bb, maxd, nlab, tile_y, band_d, base + t, c, big, key);
+        if (c) atomicAdd(&s_key[key], 1u);
+    }
+    __syncthreads();
+    {                                                  // first position of each key, costliest first
+        const uint32_t m = s_key[PLAN_KEYS - 1 - t];
+        s[0][t] = m;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t v = t >= off ? s[0][t - off] : 0u;
+            __syncthreads();
+            s[0][t] += v;
+            __syncthreads();
+        }
+        s_key[PLAN_KEYS - 1 - t] = s[0][t] - m;
+        if (t == 1023) s_np = s[0][t];
+    }
+    __syncthreads();
     for (uint32_t base = 0; base < nlab; base += 1024) {
         const uint32_t l = base + t;
-        uint32_t c = 0;
-        bool big = false;
-        if (l > 0 && l < nlab && bb[5 * nlab + l] >= 0) {
-            const int by = bb[3 * nlab + l] - bb[2 * nlab + l] + 1;
-            const int bx = bb[5 * nlab + l] - bb[4 * nlab + l] + 1;
-            c = (uint32_t)((by + tile_y - 1) / tile_y) * (uint32_t)((bx + TILE_X - 1) / TILE_X);
-            big = maxd[l] > band_d;
-            if (big) c *= (uint32_t)((bb[1 * nlab + l] - bb[0 * nlab + l] + BAND_ZCHUNK) / BAND_ZCHUNK);
+        uint32_t c;
+        bool big;
+        int key;
+        plan_items(bb, maxd, nlab, tile_y, band_d, l, c, big, key);
+        if (c) {
+            const uint32_t p = atomicAdd(&s_key[key], 1u);
+            ord[p] = l;
+            toff[p] = big ? 0u : c;                    // item counts by position, scanned below
+            toff_big[p] = big ? c : 0u;
         }
-        const uint32_t cs[2] = {big ? 0u : c, big ? c : 0u};
+    }
+    __syncthreads();                                   // the block's counts are visible to it
+    const uint32_t np = s_np;
+    uint32_t running[2] = {0u, 0u};
+    for (uint32_t base = 0; base < nlab; base += 1024) {
+        const uint32_t p = base + t;
+        const uint32_t cs[2] = {p < np ? toff[p] : 0u, p < np ? toff_big[p] : 0u};
         s[0][t] = cs[0];
         s[1][t] = cs[1];
         __syncthreads();
@@ -896,9 +970,9 @@ plan_tiles(const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd, uin
             s[1][t] += v1;
             __syncthreads();
         }
-        if (l < nlab) {
-            toff[l] = running[0] + s[0][t] - cs[0];
-            toff_big[l] = running[1] + s[1][t] - cs[1];
+        if (p < nlab) {
+            toff[p] = running[0] + s[0][t] - cs[0];
+            toff_big[p] = running[1] + s[1][t] - cs[1];
         }
         running[0] += s[0][1023];
         running[1] += s[1][1023];
@@ -1092,7 +1166,8 @@ template <int NDIM, typename L, bool W = false, bool BAND = false>
 __global__ void __launch_bounds__(PAINT_THREADS)
 paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
             const int32_t* __restrict__ kd, const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
-            const uint32_t* __restrict__ toff, uint32_t nlab, int nx, int ny, int nz, int tile_y,
+            const uint32_t* __restrict__ toff, const uint32_t* __restrict__ ord, uint32_t nlab, int nx, int ny,
+            int nz, int tile_y,
             uint32_t* __restrict__ counter, int32_t* __restrict__ lt, const uint32_t* __restrict__ spill,
             const uint32_t* __restrict__ pool, const uint32_t* __restrict__ bmap,
             const int32_t* __restrict__ colmax, int chunk, MeasureSums ms, const int32_t* __restrict__ Dmap,
@@ -1100,7 +1175,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     // dynamic LDS: the sparse table [TILE_LEVELS][tile_y][TILE_STRIDE], then one disc
     // list per wave
     extern __shared__ uint32_t M[];
-    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_item, s_pos;
     __shared__ unsigned long long s_dirty[2];      // painted rows, by slice parity
     __shared__ int s_floor[2];                     // tile floors of the banded passes
     __shared__ uint8_t s_reach[REACH_TAB];
@@ -1125,23 +1200,35 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
     }
     pd_idx[0] = 0u;
     for (;;) {
-        if (tid == 0) {
-            s_item = atomicAdd(counter, 1u);
-            s_dirty[0] = s_dirty[1] = 0ull;
-            s_floor[0] = s_floor[1] = INT_MAX;
+        if (wid == 0) {
+            // next item, and its position in the list: the largest p with toff[p] <= item,
+            // by a 64-way search (each round one load per lane narrows the range 64-fold)
+            uint32_t item = 0u;
+            if (lane == 0) item = atomicAdd(counter, 1u);
+            item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
+            uint32_t lo = 0u;
+            if (item < total) {
+                uint32_t hi = nlab;                  // toff[lo] <= item < toff[hi]
+                while (hi - lo > 1u) {
+                    const uint32_t step = (hi - lo + 63u) >> 6;
+                    const uint32_t q = lo + (uint32_t)lane * step;
+                    const unsigned long long le = __ballot(q < hi && toff[q] <= item);
+                    lo += (uint32_t)(63 - __clzll(le)) * step;
+                    hi = min(hi, lo + step);
+                }
+            }
+            if (lane == 0) {
+                s_item = item;
+                s_pos = lo;
+                s_dirty[0] = s_dirty[1] = 0ull;
+                s_floor[0] = s_floor[1] = INT_MAX;
+            }
         }
         __syncthreads();
-        const uint32_t item = s_item;
+        const uint32_t item = s_item, pos = s_pos;
         __syncthreads();
         if (item >= total) break;
-        // label: the largest l with toff[l] <= item
-        uint32_t lo = 0, hi = nlab;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (toff[mid] <= item) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t l = lo;
+        const uint32_t l = ord[pos];
         const int z0 = bb[0 * nlab + l], z1 = bb[1 * nlab + l] + 1;
         const int y0 = bb[2 * nlab + l], y1 = bb[3 * nlab + l] + 1;
         const int x0 = bb[4 * nlab + l], x1 = bb[5 * nlab + l] + 1;
@@ -1151,12 +1238,17 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
         const int Ry = W ? open_reach_w(mdl, spc.wy) : R;
         const int Rx = W ? open_reach_w(mdl, spc.wx) : R;
         const int tiles_x = (x1 - x0 + TILE_X - 1) / TILE_X;
-        int tt = (int)(item - toff[l]);
+        int tt = (int)(item - toff[pos]);
         int pz0 = NDIM == 3 ? z0 : 0, pz1 = NDIM == 3 ? z1 : 1;
-        if (BAND) {                                  // items of BAND_ZCHUNK slices each
+        if (NDIM == 3) {                             // the item's run of slices
             const int ntile = tiles_x * ((y1 - y0 + tile_y - 1) / tile_y);
-            pz0 = z0 + (tt / ntile) * BAND_ZCHUNK;
-            pz1 = min(z1, pz0 + BAND_ZCHUNK);
+            int zl = BAND_ZCHUNK;                    // banded: runs of BAND_ZCHUNK
+            if (!BAND) {                             // plain: ceil(bz / PLAIN_ZCHUNK) equal runs
+                const int nzc = (z1 - z0 + PLAIN_ZCHUNK - 1) / PLAIN_ZCHUNK;
+                zl = (z1 - z0 + nzc - 1) / nzc;
+            }
+            pz0 = z0 + (tt / ntile) * zl;
+            pz1 = min(z1, pz0 + zl);
             tt %= ntile;
         }
         TileCtx t;
@@ -1533,7 +1625,7 @@ paint_tiles(const L* __restrict__ lab, const uint32_t* __restrict__ zf,
 static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct ThickLayout {
-    size_t bb, maxd, toff, toff_big, counter, zf, kd, spill, colmax, work, pool, bmap, total;
+    size_t bb, maxd, toff, toff_big, ord, counter, zf, kd, spill, colmax, work, pool, bmap, total;
     uint32_t wcap;          // long-list work items: one per (column, chunk) at the smallest chunk
     size_t pool_words;
 };
@@ -1546,6 +1638,7 @@ static ThickLayout thick_layout(const Geom& g, uint32_t max_label) {
     o.maxd = at;    at += align256(nlab * sizeof(int32_t));
     o.toff = at;    at += align256((nlab + 1) * sizeof(uint32_t));
     o.toff_big = at; at += align256((nlab + 1) * sizeof(uint32_t));
+    o.ord = at;     at += align256(nlab * sizeof(uint32_t));
     o.counter = at; at += 256;
     o.zf = at;      at += align256((g.ndim == 3 ? ZF_PLANES : 1) * g.n * sizeof(uint32_t));
     o.kd = at;      at += g.ndim == 3 ? align256(g.n * sizeof(int32_t)) : 0;
@@ -1632,6 +1725,7 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     int32_t* maxd = (int32_t*)(base + lay.maxd);
     uint32_t* toff = (uint32_t*)(base + lay.toff);
     uint32_t* toff_big = (uint32_t*)(base + lay.toff_big);
+    uint32_t* ord = (uint32_t*)(base + lay.ord);
     uint32_t* counter = (uint32_t*)(base + lay.counter);
     uint32_t* zf = (uint32_t*)(base + lay.zf);
     int32_t* kd = (int32_t*)(base + lay.kd);
@@ -1715,7 +1809,7 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
     const int band_d = BAND_REACH * BAND_REACH * std::min(sp.wy, sp.wx);
     {
         ProfScope _p(ctx, s, "plan_tiles");
-        plan_tiles<<<1, 1024, 0, s>>>(bb, maxd, nlab, tile_y, band_d, toff, toff_big, counter);
+        plan_tiles<<<1, 1024, 0, s>>>(bb, maxd, nlab, tile_y, band_d, toff, toff_big, ord, counter);
     }
     // two blocks of 512 threads per CU (32-row tiles) when both fit in the LDS, else one
     // block of 1024 threads: two blocks overlap each other's slice barriers
@@ -1730,20 +1824,20 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             ProfScope _p(ctx, s, "paint_tiles_banded");
             if (w)
                 paint_tiles<3, L, true, true><<<blocks, threads, lds, s>>>(
-                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
+                    lab, zf, kd, bb, maxd, toff_big, ord, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
                     pool.base, bmap, colmax, chunk, ms, D, sp);
             else
                 paint_tiles<3, L, false, true><<<blocks, threads, lds, s>>>(
-                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
+                    lab, zf, kd, bb, maxd, toff_big, ord, nlab, g.nx, g.ny, g.nz, tile_y, counter + 6, lt, spill,
                     pool.base, bmap, colmax, chunk, ms, D);
         }
         ProfScope _p(ctx, s, "paint_tiles");
         if (w)
-            paint_tiles<3, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
+            paint_tiles<3, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, ord, nlab, g.nx, g.ny, g.nz,
                                                                  tile_y, counter, lt, spill, pool.base, bmap, colmax,
                                                                  chunk, ms, D, sp);
         else
-            paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, g.nz,
+            paint_tiles<3, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, ord, nlab, g.nx, g.ny, g.nz,
                                                            tile_y, counter, lt, spill, pool.base, bmap, colmax, chunk,
                                                            ms, D);
     } else {
@@ -1751,20 +1845,20 @@ static lt_status thickness_typed(lt_ctx* ctx, const L* lab, const Geom& g, const
             ProfScope _p(ctx, s, "paint_tiles_banded");
             if (w)
                 paint_tiles<2, L, true, true><<<blocks, threads, lds, s>>>(
-                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
+                    lab, zf, kd, bb, maxd, toff_big, ord, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
                     bmap, nullptr, chunk, ms, D, sp);
             else
                 paint_tiles<2, L, false, true><<<blocks, threads, lds, s>>>(
-                    lab, zf, kd, bb, maxd, toff_big, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
+                    lab, zf, kd, bb, maxd, toff_big, ord, nlab, g.nx, g.ny, 1, tile_y, counter + 6, lt, spill, pool.base,
                     bmap, nullptr, chunk, ms, D);
         }
         ProfScope _p(ctx, s, "paint_tiles");
         if (w)
-            paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1,
+            paint_tiles<2, L, true><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, ord, nlab, g.nx, g.ny, 1,
                                                                  tile_y, counter, lt, spill, pool.base, bmap, nullptr,
                                                                  chunk, ms, D, sp);
         else
-            paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, nlab, g.nx, g.ny, 1, tile_y,
+            paint_tiles<2, L><<<blocks, threads, lds, s>>>(lab, zf, kd, bb, maxd, toff, ord, nlab, g.nx, g.ny, 1, tile_y,
                                                            counter, lt, spill, pool.base, bmap, nullptr, chunk, ms,
                                                            D);
     }

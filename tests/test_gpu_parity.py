@@ -247,6 +247,42 @@ def test_deterministic_repeat(gpu):
         np.testing.assert_array_equal(a[k], b[k])
 
 
+def _ball_and_smalls():
+    """A digital ball of radius 45 (largest D 2026: the banded paint list) and eight
+    balls of radius 4..11 (the plain list) beside it in a 128^3 volume."""
+    vol = np.zeros((128, 128, 128), dtype=np.int32)
+    m, _ = synth.ball_mask(45)
+    vol[1:1 + m.shape[0], 1:1 + m.shape[1], 1:1 + m.shape[2]][m] = 1
+    for i, r in enumerate(range(4, 12)):
+        m, _ = synth.ball_mask(r)
+        z, y = 2 + 30 * (i // 2), 2 + 40 * (i % 2)
+        vol[z:z + m.shape[0], y:y + m.shape[1], 98:98 + m.shape[2]][m] = i + 2
+    return vol
+
+
+@pytest.mark.parametrize("case", ["cfg2", "ball_and_smalls"])
+def test_label_numbering_does_not_change_results(gpu, case):
+    """The paint work items are ordered by estimated cost, not by label: renumbering
+    the objects (random and reversed) leaves D and LT unchanged bit for bit and
+    permutes the per-object measures with the labels."""
+    lab = synth.cfg2()[0] if case == "cfg2" else _ball_and_smalls()
+    k = int(lab.max())
+    base = run_gpu(gpu, lab)
+    if case == "ball_and_smalls":                 # a digital ball of radius r: LT^2 = r^2 + 1
+        for l, r in [(1, 45)] + [(i + 2, r) for i, r in enumerate(range(4, 12))]:
+            assert np.all(base["lt_sq"][lab == l] == r * r + 1)
+    rng = np.random.default_rng(11)
+    for name, perm in (("random", rng.permutation(k) + 1), ("reversed", np.arange(k, 0, -1))):
+        _note(f"{case}: {name} numbering")
+        lut = np.zeros(k + 1, dtype=lab.dtype)
+        lut[1:] = perm
+        got = run_gpu(gpu, lut[lab], max_label=k)
+        np.testing.assert_array_equal(got["dist_sq"], base["dist_sq"])
+        np.testing.assert_array_equal(got["lt_sq"], base["lt_sq"])
+        for key in ("volume", "shell_count", "max_lt_sq") + FLOAT_KEYS:
+            np.testing.assert_array_equal(got[key][perm], base[key][1:k + 1], err_msg=f"{name}: {key}")
+
+
 def test_closed_forms_entry_fp32_vs_fp64(gpu):
     """The FP32 closed forms over a wide range of volumes and mean thickness,
     including near-spheres and extreme oblate / prolate spheroids."""
