@@ -212,7 +212,11 @@ __global__ void init_boxes(int32_t* bb, uint32_t nlab) {
 // With W (anisotropic spacing) a step k along the axis costs wa k^2 (wa = the
 // squared spacing of the axis) and the y pass stages w_x g^2 in the word form of
 // the z pass.
-constexpr int LINE_T = 64, LINE_H = 32, LINE_ROWS = LINE_T + 2 * LINE_H;
+constexpr int LINE_T = 64, LINE_H = 24, LINE_ROWS = LINE_T + 2 * LINE_H;
+// Staged row r is held by the wave r mod 8 (rows ty + 8 q); the output rows LINE_H + ty
+// + 8 j must be the waves' own staged rows (the y pass reads its per-row flags from
+// registers), so the halo is a multiple of the wave count.
+static_assert(LINE_H % 8 == 0 && LINE_T % 8 == 0, "line-pass rows must stay with their staging wave");
 constexpr uint32_t LINE_BLK_DN = 1u << 31, LINE_BLK_UP = 1u << 30, LINE_VAL = LINE_BLK_UP - 1u;
 
 // Value a staged word offers a search walking down (up) to it: its value, or 0 when
