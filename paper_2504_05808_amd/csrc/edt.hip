@@ -35,7 +35,7 @@ namespace lt {
 // global boxes once per block.  The next row's labels are loaded while a row is
 // processed.
 constexpr int XBOX_TAB = 128;
-constexpr int XW = 16;                               // waves per block of the x pass
+constexpr int XW = 4;                                // waves per block of the x pass
 constexpr int XRUNS = 64;                            // run list entries per wave
 
 template <typename L, bool BOX, int MAXC>
@@ -365,7 +365,9 @@ static lt_status edt_typed(lt_ctx* ctx, const L* lab, const Geom& g, int32_t* di
     {
         ProfScope _p(ctx, s, "edt_pass_x");
         const int chunks = (g.nx + 63) / 64;
-        const int gz = loop_extent(g.nz, g.ny, ctx, 4);
+        // many small blocks (about 32 per compute unit): 0.27 ms at 512^3 against 0.38 with
+        // 16 waves and 4 blocks per unit
+        const int gz = loop_extent(g.nz, g.ny, ctx, 32);
         const int zper = (g.nz + gz - 1) / gz;
         const int nzb = (g.nz + zper - 1) / zper;
         const dim3 grid(1, g.ny, nzb);
