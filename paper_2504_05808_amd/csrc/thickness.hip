@@ -561,16 +561,27 @@ fronts3d(const int32_t* __restrict__ kd, int nx, int ny, int nz, int chunk,
             bacc1 = max(bacc1, cm);
             continue;
         }
+        if (cnt == 0) {                               // no listed ball reaches the chunk
+            for (int z = c0 + lane; z < c1; z += 64) out[(z - zs) * FZ_STRIDE] = 0u;
+            continue;
+        }
         if (lane < 4) list[cnt + lane] = 0u;          // padding: keys 0 count for no entry
         wave_lds_sync();
         // rank of each entry = number of larger keys (keys are distinct: one z each)
         const uint32_t e0 = lane < cnt ? list[lane] : 0u;
         const uint32_t e1 = lane + 64 < cnt ? list[lane + 64] : 0u;
         int r0 = 0, r1 = 0;
-        for (int k = 0; k < cnt; k += 4) {
-            const uint4 q = *(const uint4*)(list + k);
-            r0 += (q.x > e0) + (q.y > e0) + (q.z > e0) + (q.w > e0);
-            r1 += (q.x > e1) + (q.y > e1) + (q.z > e1) + (q.w > e1);
+        if (cnt > 64) {                               // two entries per lane
+            for (int k = 0; k < cnt; k += 4) {
+                const uint4 q = *(const uint4*)(list + k);
+                r0 += (q.x > e0) + (q.y > e0) + (q.z > e0) + (q.w > e0);
+                r1 += (q.x > e1) + (q.y > e1) + (q.z > e1) + (q.w > e1);
+            }
+        } else {
+            for (int k = 0; k < cnt; k += 4) {
+                const uint4 q = *(const uint4*)(list + k);
+                r0 += (q.x > e0) + (q.y > e0) + (q.z > e0) + (q.w > e0);
+            }
         }
         // the list area now takes the entries by rank as (zc, v - zc^2), padded to a
         // multiple of four with entries no slice takes
