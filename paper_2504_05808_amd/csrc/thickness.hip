@@ -873,18 +873,19 @@ constexpr int NBANDS = 3;            // value bands of the banded launch
 
 // Paint work items of the present objects, split by size: objects whose largest D
 // exceeds band_d (balls reaching BAND_REACH or more along y or x) go to toff_big and
-// the banded paint launch, one item per (tile, BAND_ZCHUNK slices); the rest to toff,
-// one item per (tile, run of at most PLAIN_ZCHUNK slices; an object of bz slices is cut
-// into ceil(bz / PLAIN_ZCHUNK) runs of equal length, the last shorter).  Both launches run a persistent grid that
-// takes items in list order, so the lists are ordered by estimated cost, longest
-// first, whatever the numbering of the labels (list scheduling ends evenly when the
-// long items go first): each present object gets a key, the class of its per-item
-// work (slices x rows x columns of an item times the reach of its largest ball, plus
-// one) in steps of a quarter octave; positions are given out key by key from the costliest down (in
-// arrival order within a key), ord[position] = label, and toff / toff_big are
-// exclusive scans over positions of the objects' item counts.  Positions past the
-// present objects hold no items.  toff and toff_big have nlab + 1 entries; entry nlab
-// is the total.  One block of 1024 threads.
+// the banded paint launch, one item per (tile, BAND_ZCHUNK slices); the rest go to
+// toff, one item per (tile, run of slices): an object of bz slices is cut into
+// ceil(bz / PLAIN_ZCHUNK) runs of ceil(bz / runs) slices, the last one shorter.
+// Both launches run a persistent grid that takes items in list order, so the lists
+// are ordered by estimated cost, longest first, whatever the numbering of the labels
+// (list scheduling ends evenly when the long items go first): each present object
+// gets a key, the quarter-octave class of its per-item work (slices x rows x columns
+// of one item times the reach of its largest ball, plus one); positions are given
+// out key by key from the costliest down (in arrival order within a key),
+// ord[position] = label, and toff / toff_big are exclusive scans over positions of
+// the objects' item counts.  Positions past the present objects hold no items.  toff
+// and toff_big have nlab + 1 entries; entry nlab is the total.  One block of 1024
+// threads.
 constexpr int PLAN_KEYS = 1024;            // one per thread of the block
 constexpr int PLAIN_ZCHUNK = 24;
 
