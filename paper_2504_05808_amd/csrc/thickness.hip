@@ -892,15 +892,19 @@ constexpr int PLAIN_ZCHUNK = 24;
 __device__ __forceinline__ void plan_items(const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd,
                                            uint32_t nlab, int tile_y, int band_d, uint32_t l, uint32_t& c,
                                            bool& big, int& key) {
+    // every load issued before any test, so that several labels' loads are in flight
+    const bool in = l > 0u && l < nlab;
+    const uint32_t li = in ? l : 0u;
+    const int z0 = bb[0 * nlab + li], z1 = bb[1 * nlab + li];
+    const int y0 = bb[2 * nlab + li], y1 = bb[3 * nlab + li];
+    const int x0 = bb[4 * nlab + li], x1 = bb[5 * nlab + li];
+    const int md = max(maxd[li], 1);
     c = 0u;
     big = false;
     key = 0;
-    if (l == 0u || l >= nlab || bb[5 * nlab + l] < 0) return;
-    const int bz = bb[1 * nlab + l] - bb[0 * nlab + l] + 1;
-    const int by = bb[3 * nlab + l] - bb[2 * nlab + l] + 1;
-    const int bx = bb[5 * nlab + l] - bb[4 * nlab + l] + 1;
+    if (!in || x1 < 0) return;                         // label 0, or absent
+    const int bz = z1 - z0 + 1, by = y1 - y0 + 1, bx = x1 - x0 + 1;
     const int ty = (by + tile_y - 1) / tile_y, tx = (bx + TILE_X - 1) / TILE_X;
-    const int md = max(maxd[l], 1);
     c = (uint32_t)(ty * tx);
     big = md > band_d;
     int zi = bz;                                       // slices of one item
@@ -920,79 +924,101 @@ __device__ __forceinline__ void plan_items(const int32_t* __restrict__ bb, const
     key = min(PLAN_KEYS - 1, (e << 2) | frac);
 }
 
+// Exclusive scan of (a0, a1) over the 1024 threads of the block in thread order (wave
+// scans, then the 16 wave totals from LDS); tot0 / tot1 are the block totals.  Every
+// thread calls it; it ends with a barrier, so s_w can be used again at once.
+__device__ __forceinline__ void plan_block_scan(uint32_t a0, uint32_t a1, uint32_t& e0, uint32_t& e1,
+                                                uint32_t& tot0, uint32_t& tot1, uint32_t (*s_w)[16]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t i0 = (uint32_t)wave_scan_add((int)a0), i1 = (uint32_t)wave_scan_add((int)a1);
+    if (lane == 63) {
+        s_w[0][w] = i0;
+        s_w[1][w] = i1;
+    }
+    __syncthreads();
+    uint32_t o0 = 0u, o1 = 0u;
+    tot0 = tot1 = 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t v0 = s_w[0][q], v1 = s_w[1][q];
+        o0 += q < w ? v0 : 0u;
+        o1 += q < w ? v1 : 0u;
+        tot0 += v0;
+        tot1 += v1;
+    }
+    e0 = o0 + i0 - a0;
+    e1 = o1 + i1 - a1;
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(1024)
 plan_tiles(const int32_t* __restrict__ bb, const int32_t* __restrict__ maxd, uint32_t nlab, int tile_y,
            int band_d, uint32_t* __restrict__ toff, uint32_t* __restrict__ toff_big, uint32_t* __restrict__ ord,
            uint32_t* __restrict__ counter) {
-    __shared__ uint32_t s[2][1024];
+    constexpr int PU = 4;                              // labels per thread per round
     __shared__ uint32_t s_key[PLAN_KEYS];              // objects per key, then the key's next position
+    __shared__ uint32_t s_w[2][16];
     __shared__ uint32_t s_np;
     const int t = threadIdx.x;
     s_key[t] = 0u;
     __syncthreads();
-    for (uint32_t base = 0; base < nlab; base += 1024) {
-        uint32_t c;
-        bool big;
-        int key;
-        plan_items(bb, maxd, nlab, tile_y, band_d, base + t, c, big, key);
-        if (c) atomicAdd(&s_key[key], 1u);
+    for (uint32_t base = 0; base < nlab; base += PU * 1024) {
+        uint32_t c[PU];
+        bool big[PU];
+        int key[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) plan_items(bb, maxd, nlab, tile_y, band_d, base + u * 1024 + t, c[u], big[u], key[u]);
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            if (c[u]) atomicAdd(&s_key[key[u]], 1u);
     }
     __syncthreads();
     {                                                  // first position of each key, costliest first
         const uint32_t m = s_key[PLAN_KEYS - 1 - t];
-        s[0][t] = m;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t v = t >= off ? s[0][t - off] : 0u;
-            __syncthreads();
-            s[0][t] += v;
-            __syncthreads();
-        }
-        s_key[PLAN_KEYS - 1 - t] = s[0][t] - m;
-        if (t == 1023) s_np = s[0][t];
+        uint32_t e, e_, tot, tot_;
+        plan_block_scan(m, 0u, e, e_, tot, tot_, s_w);
+        s_key[PLAN_KEYS - 1 - t] = e;
+        if (t == 0) s_np = tot;
     }
     __syncthreads();
-    for (uint32_t base = 0; base < nlab; base += 1024) {
-        const uint32_t l = base + t;
-        uint32_t c;
-        bool big;
-        int key;
-        plan_items(bb, maxd, nlab, tile_y, band_d, l, c, big, key);
-        if (c) {
-            const uint32_t p = atomicAdd(&s_key[key], 1u);
-            ord[p] = l;
-            toff[p] = big ? 0u : c;                    // item counts by position, scanned below
-            toff_big[p] = big ? c : 0u;
-        }
+    for (uint32_t base = 0; base < nlab; base += PU * 1024) {
+        uint32_t c[PU];
+        bool big[PU];
+        int key[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) plan_items(bb, maxd, nlab, tile_y, band_d, base + u * 1024 + t, c[u], big[u], key[u]);
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            if (c[u]) {
+                const uint32_t p = atomicAdd(&s_key[key[u]], 1u);
+                ord[p] = base + u * 1024 + t;
+                toff[p] = big[u] ? 0u : c[u];          // item counts by position, scanned below
+                toff_big[p] = big[u] ? c[u] : 0u;
+            }
     }
     __syncthreads();                                   // the block's counts are visible to it
     const uint32_t np = s_np;
-    uint32_t running[2] = {0u, 0u};
-    for (uint32_t base = 0; base < nlab; base += 1024) {
+    uint32_t run0 = 0u, run1 = 0u;                     // the same in every thread
+    uint32_t base = 0;
+    for (; base < np; base += 1024) {
         const uint32_t p = base + t;
-        const uint32_t cs[2] = {p < np ? toff[p] : 0u, p < np ? toff_big[p] : 0u};
-        s[0][t] = cs[0];
-        s[1][t] = cs[1];
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t v0 = t >= off ? s[0][t - off] : 0u;
-            const uint32_t v1 = t >= off ? s[1][t - off] : 0u;
-            __syncthreads();
-            s[0][t] += v0;
-            s[1][t] += v1;
-            __syncthreads();
-        }
+        const uint32_t a0 = p < np ? toff[p] : 0u, a1 = p < np ? toff_big[p] : 0u;
+        uint32_t e0, e1, t0, t1;
+        plan_block_scan(a0, a1, e0, e1, t0, t1, s_w);
         if (p < nlab) {
-            toff[p] = running[0] + s[0][t] - cs[0];
-            toff_big[p] = running[1] + s[1][t] - cs[1];
+            toff[p] = run0 + e0;
+            toff_big[p] = run1 + e1;
         }
-        running[0] += s[0][1023];
-        running[1] += s[1][1023];
-        __syncthreads();
+        run0 += t0;
+        run1 += t1;
+    }
+    for (uint32_t p = base + t; p < nlab; p += 1024) {   // positions past the objects: no items
+        toff[p] = run0;
+        toff_big[p] = run1;
     }
     if (t == 0) {
-        toff[nlab] = running[0];
-        toff_big[nlab] = running[1];
+        toff[nlab] = run0;
+        toff_big[nlab] = run1;
         counter[0] = 0u;                               // work items of the two paint launches
         counter[6] = 0u;
     }
